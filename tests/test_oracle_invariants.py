@@ -1,0 +1,139 @@
+"""Pins the oracle against properties that eq. (1) fixes for special rates and
+states, and against the phases the paper reports (Sec. 2 and Sec. 5.3)."""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1301_6082_amd import workloads
+
+
+def _per_sample(run):
+    return run.n.astype(np.int64), run.pair.astype(np.int64)
+
+
+def _rand_init(L, density, seed):
+    return workloads.random_lattice(L, 1, density, seed)
+
+
+@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd"])
+def test_pure_diffusion_conserves_particles(model):
+    L = 256
+    init = _rand_init(L, 0.4, 1)
+    r = oracle.simulate(oracle.Run(model=model, L=L, p=0.3, d=1.0, init="host",
+                                   init_words=init, times=list(range(0, 41, 5))))
+    n, _ = _per_sample(r)
+    start = np.array([bin(int(w)).count("1") for w in init])  # not per sample
+    per_sample0 = np.array([sum((int(w) >> b) & 1 for w in init) for b in range(64)])
+    assert (n == per_sample0[None, :]).all()
+    assert start.sum() == per_sample0.sum()
+
+
+def test_pure_annihilation_never_creates_particles():
+    L = 512
+    r = oracle.simulate(oracle.Run(L=L, p=1.0, d=0.0, init="host",
+                                   init_words=_rand_init(L, 0.7, 2),
+                                   times=list(range(0, 31))))
+    n, _ = _per_sample(r)
+    assert (np.diff(n, axis=0) <= 0).all()
+    assert (np.diff(n, axis=0) % 2 == 0).all()   # pairs vanish two at a time
+    assert (np.diff(n, axis=0) < 0).any()
+
+
+def test_pure_fission_never_removes_particles():
+    L = 512
+    r = oracle.simulate(oracle.Run(L=L, p=0.0, d=0.0, init="host",
+                                   init_words=_rand_init(L, 0.2, 3),
+                                   times=list(range(0, 31))))
+    n, _ = _per_sample(r)
+    assert (np.diff(n, axis=0) >= 0).all()
+    assert (np.diff(n, axis=0) > 0).any()
+
+
+@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd"])
+def test_empty_lattice_is_absorbing(model):
+    r = oracle.simulate(oracle.Run(model=model, L=256, p=0.1, d=0.5, init="empty",
+                                   times=[1, 5, 20]))
+    assert (r.n == 0).all() and (r.words == 0).all()
+
+
+def test_lone_particle_is_absorbing_for_pcpd():
+    L = 256
+    init = np.zeros(L, dtype=np.uint64)
+    rng = np.random.default_rng(4)
+    for b in range(64):
+        init[rng.integers(L)] |= np.uint64(1) << np.uint64(b)
+    r = oracle.simulate(oracle.Run(L=L, p=0.05, d=0.3, init="host", init_words=init,
+                                   times=list(range(1, 60, 3))))
+    assert (r.n == 1).all()
+    assert (r.pair == 0).all()
+
+
+def test_two_particles_are_frozen_in_number_for_tcpd():
+    L = 128
+    init = np.zeros(L, dtype=np.uint64)
+    rng = np.random.default_rng(5)
+    for b in range(64):
+        i, j = rng.choice(L, size=2, replace=False)
+        init[i] |= np.uint64(1) << np.uint64(b)
+        init[j] |= np.uint64(1) << np.uint64(b)
+    r = oracle.simulate(oracle.Run(model="tcpd", L=L, p=0.05, d=0.3, init="host",
+                                   init_words=init, times=list(range(1, 40, 3))))
+    assert (r.n == 2).all()
+
+
+def test_dp_single_particle_can_spread():
+    L = 256
+    init = np.zeros(L, dtype=np.uint64)
+    init[10] = np.uint64(2**64 - 1)
+    r = oracle.simulate(oracle.Run(model="dp", L=L, p=0.05, d=0.1, init="host",
+                                   init_words=init, times=[20]))
+    assert r.n.max() > 1
+
+
+def test_full_start_counts_and_bounds():
+    L = 1024
+    r = oracle.simulate(oracle.Run(L=L, p=0.1, d=0.5, times=[0, 1, 10, 100]))
+    n, pair = _per_sample(r)
+    assert (n[0] == L).all() and (pair[0] == L).all()
+    assert (pair <= n).all() and (n <= L).all()
+
+
+def test_resume_equals_uninterrupted_run():
+    """State is only (lattice, t): stopping at t1 and restarting from the
+    stored lattice with t0 = t1 must give the same lattice and counts."""
+    L = 640
+    kw = dict(model="pcpd", B=64, L=L, seed=9, stream=3, plane=2, p=0.12, d=0.3)
+    full = oracle.simulate(oracle.Run(**kw, times=[7, 19]))
+    first = oracle.simulate(oracle.Run(**kw, times=[7]))
+    second = oracle.simulate(oracle.Run(**kw, init="host", init_words=first.words, t0=7,
+                                        times=[19]))
+    assert (second.words == full.words).all()
+    assert (second.n[0] == full.n[1]).all() and (second.pair[0] == full.pair[1]).all()
+    assert (first.n[0] == full.n[0]).all()
+
+
+def test_sample_subsets_evolve_independently():
+    """Each sample's trajectory depends only on its own bits: simulating a
+    subset of the 64 samples reproduces those samples of the full run."""
+    L = 320
+    kw = dict(model="pcpd", B=64, L=L, seed=1, stream=2, plane=1, p=0.15, d=0.2,
+              times=[3, 9])
+    full = oracle.simulate(oracle.Run(**kw))
+    mask = (1 << 5) | (1 << 40) | (1 << 63)
+    part = oracle.simulate(oracle.Run(**kw, samples=mask))
+    assert (part.words == (full.words & np.uint64(mask))).all()
+    for b in (5, 40, 63):
+        assert (part.n[:, b] == full.n[:, b]).all()
+
+
+@pytest.mark.parametrize("d,p_active,p_inactive", [(0.25, 0.05, 0.30), (0.75, 0.12, 0.35)])
+def test_phases_on_either_side_of_the_papers_critical_rate(d, p_active, p_inactive):
+    """Paper Sec. 5.3: p_c(d=0.25) = 0.125141, p_c(d=0.75) = 0.191789. Well
+    below p_c the density stays finite; well above it decays towards zero."""
+    L = 1024
+    act = oracle.simulate(oracle.Run(L=L, p=p_active, d=d, times=[1500]))
+    ina = oracle.simulate(oracle.Run(L=L, p=p_inactive, d=d, times=[1500]))
+    rho_act = act.n.sum() / (64 * L)
+    rho_ina = ina.n.sum() / (64 * L)
+    assert rho_act > 0.1
+    assert rho_ina < 0.02
