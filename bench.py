@@ -1,0 +1,166 @@
+"""Benchmark: site-updates/s of the multispin PCPD sweep on one MI355X.
+
+Workload: PCPD, periodic ring L = 2^20, 4 planes of 64 samples (256 samples),
+d = 0.1, 16 values of p = linspace(0.05, 0.20, 16), fully occupied start,
+Philox seed 1, density recorded at the 64 log-spaced times of a 10^5-step run.
+One benchmark step = 1000 Monte Carlo steps of all 16 x 4 planes (4.3e12
+site updates), with the density records that fall inside it plus one at its
+end; consecutive steps continue the same trajectory, so warmup + timed steps
+cover a prefix of the 10^5-step run.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mc-per-step M]
+
+Prints one JSON line. Also reports the dominant kernel (the phase kernel of
+the sweep) against the integer-VALU roofline, and the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Integer-VALU op model of one word-update (64 site updates): issue slots of
+# the algorithm's arithmetic, counted on gfx950 with 32x32->64 multiplies at a
+# quarter of the full rate (see the design notes for the derivation).
+OPS_PER_WORD_UPDATE = 352
+PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x lanes x clock: 3.93e13 slots/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mc-per-step", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-units", type=int, default=8)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, n_units: int):
+    """The oracle as it stands, on (instance, plane) units of the same
+    workload, 2 MC steps each, all host cores (OpenMP over units)."""
+    from oracle import oracle
+
+    oracle.build(force=False)
+    units = []
+    steps = 2
+    for u in range(n_units):
+        i, q = u % len(wl.instances), (u // len(wl.instances)) % wl.planes
+        inst = wl.instances[i]
+        units.append(oracle.Run(model="pcpd", B=wl.B, L=inst.L, seed=wl.seed,
+                                stream=inst.stream_id, plane=q, p=inst.p, d=inst.d,
+                                times=[steps]))
+    threads = min(oracle.max_threads(), n_units)
+    t0 = time.perf_counter()
+    oracle.simulate_many(units, n_threads=threads)
+    dt = time.perf_counter() - t0
+    su = sum(64 * r.params.L * steps for r in units)
+    return {"value": su / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_units} (instance, plane) units of the workload, L=2^20, 64 samples "
+                      f"each, {steps} MC steps from the full start ({su:.3e} site updates, "
+                      f"{dt:.1f} s wall)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the instances shard across GPUs with no exchange, but this build runs on one).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1301_6082_amd import pcpd
+    from paper_1301_6082_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    M = args.mc_per_step
+    total_steps = (args.warmup + args.steps) * M
+    wl = workloads.cfg2()
+    rec_times = [t for t in wl.times]
+    su_per_mc = sum(64 * wl.planes * inst.L for inst in wl.instances)
+
+    sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
+    stream = torch.cuda.current_stream()
+
+    def step_times(k):
+        lo, hi = k * M, (k + 1) * M
+        ts = [t for t in rec_times if lo < t < hi]
+        return ts + [hi]
+
+    for k in range(args.warmup):
+        sim.run(step_times(k))
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    counts = None
+    for k in range(args.warmup, args.warmup + args.steps):
+        counts = sim.run(step_times(k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert sim.time == total_steps
+    site_updates = su_per_mc * M * args.steps
+    value = site_updates / elapsed
+
+    # dominant kernel: the phase kernel, timed with events on its stream
+    tuning = sim.get_tuning()
+    phases_per_mc = -(-wl.B // tuning[1])
+    n_probe = 200
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.sweep(n_probe)
+    ev1.record(stream)
+    ev1.synchronize()
+    launch_ms = ev0.elapsed_time(ev1) / (n_probe * phases_per_mc)
+    word_updates_per_launch = su_per_mc / 64 / phases_per_mc
+    ops_per_launch = OPS_PER_WORD_UPDATE * word_updates_per_launch
+    achieved = ops_per_launch / (launch_ms * 1e-3)
+    rho = counts[-1, :, :, 0].astype(np.float64).sum(axis=1) / (64 * wl.planes * (1 << 20))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_sample_units)
+
+    out = {
+        "metric": "site-updates/sec (samples x sites x MC steps) at 1 GPU",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "L": 1 << 20, "planes": wl.planes,
+                   "samples_per_instance": 64 * wl.planes, "instances": len(wl.instances),
+                   "d": 0.1, "p": "linspace(0.05,0.20,16)", "B": wl.B,
+                   "mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
+                   "records": "64 log-spaced times of a 1e5-step run, plus each step end",
+                   "tile_cols": tuning[0], "phase_max": tuning[1]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                     "unit": "Tslot/s (int32 VALU issue slots)",
+                     "frac": achieved / PEAK_SLOTS, "traffic": None,
+                     "kernel": "brs_phase<2>", "launch_ms": launch_ms,
+                     "ops_per_word_update": OPS_PER_WORD_UPDATE},
+        "cpu_baseline": cpu,
+        "rho_at_end": [round(float(x), 5) for x in rho],
+    }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

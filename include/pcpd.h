@@ -1,0 +1,165 @@
+/*
+ * pcpd.h -- C ABI of libpcpd, the MI355X (gfx950) multispin Monte Carlo sweep
+ * of 1+1-dimensional reaction-diffusion models: directed percolation (DP),
+ * the pair contact process with diffusion (PCPD) and the triplet contact
+ * process with diffusion (TCPD), after R.D. Schram, arXiv:1301.6082.
+ *
+ * What the library computes (all of it on the GPU):
+ *   - The model (paper Sec. 2, eq. (1)): on a ring of L sites, attempted
+ *     reactions AA0 -> AAA and 0AA -> AAA each with rate (1-p)(1-d)/2,
+ *     AA -> 00 with rate p(1-d), A0 <-> 0A with rate d. The n-tuple form
+ *     generalises "AA" to n particles (DP n = 1, PCPD n = 2, TCPD n = 3).
+ *   - One attempt (paper Algorithm 1): diffusion swaps sites j and j+1 with
+ *     probability d; otherwise an n-tuple at j..j+n-1 annihilates with
+ *     probability p, else a particle is created at j+n (R = 1, "high") or
+ *     at j-1 (R = 0, "low").
+ *   - Site selection (paper Sec. 3): the ring is cut into blocks of B sites;
+ *     every block is attempted at one shared, uniformly drawn local site per
+ *     substep; B substeps form one Monte Carlo step (time + 1).
+ *   - Multispin storage (paper Sec. 4): bit b of a 64-bit word is sample b;
+ *     a plane is L words (64 samples); an instance has `planes` planes.
+ *   - Random numbers: Philox-4x32-10 (Salmon et al., SC'11), key
+ *     (seed, stream_id), counter (k, 8*plane + draw, lo32 s, hi32 s) for
+ *     window k of substep s = t*B + b; draw 7 with k = 0 gives the substep
+ *     offset o = (x0 * B) >> 32. A probability-q decision of sample b is
+ *     (2*bit_b(X1) + bit_b(X2)) * 2^32 + g < rint(q * 2^34), g shared by the
+ *     64 samples of a word; this generalises the AND/OR masks of paper
+ *     Sec. 4.2 and the shared comparison RNG() < 4p of Sec. 4.3.
+ *   - Observables (paper Sec. 5.3): per (instance, plane) the particle
+ *     count N, the nearest-neighbour pair count N_pair and the mask of
+ *     samples that still hold a particle.
+ *
+ * Conventions:
+ *   - Every function returns a pcpd_status (0 = success, < 0 = error); no
+ *     C++ exception crosses this boundary.
+ *   - Host pointers are borrowed for the duration of the call only.
+ *   - Device pointers given in pcpd_device are borrowed for the lifetime of
+ *     the context and must stay valid until pcpd_free.
+ *   - Work is enqueued on the context's HIP stream. pcpd_sweep returns
+ *     before the GPU finishes; errors of enqueued work surface at the next
+ *     call that synchronises (pcpd_density, pcpd_run, pcpd_get_lattice,
+ *     pcpd_sync) as PCPD_EDEVICE. After PCPD_EDEVICE the context answers
+ *     PCPD_ESTATE to everything except pcpd_free.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef PCPD_H
+#define PCPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef PCPD_API
+#define PCPD_API __attribute__((visibility("default")))
+#endif
+
+typedef enum {
+    PCPD_OK = 0,
+    PCPD_EINVAL = -1,     /* an argument is out of range; nothing was changed */
+    PCPD_ENOMEM = -2,     /* a device or host allocation failed */
+    PCPD_EDEVICE = -3,    /* a HIP call or enqueued kernel failed */
+    PCPD_ESTATE = -4,     /* the context is unusable after an earlier device error */
+    PCPD_EOVERFLOW = -5   /* the substep counter t*B would leave 64 bits */
+} pcpd_status;
+
+typedef enum { PCPD_DP = 1, PCPD_PCPD = 2, PCPD_TCPD = 3 } pcpd_model; /* = tuple size n */
+
+typedef enum { PCPD_INIT_FULL = 0, PCPD_INIT_EMPTY = 1, PCPD_INIT_HOST = 2 } pcpd_init_kind;
+
+/* Shared by all instances of a context. */
+typedef struct {
+    int32_t model;    /* pcpd_model */
+    uint32_t B;       /* block width; B >= n+2; every L must be a multiple of B */
+    uint32_t planes;  /* planes per instance, >= 1; 64 samples each */
+    uint32_t seed;    /* Philox key word 0 */
+} pcpd_config;
+
+/* One independent simulation (its own rates, ring length and Philox stream). */
+typedef struct {
+    double p;                   /* annihilation parameter of eq. (1), 0 <= p <= 1 */
+    double d;                   /* diffusion rate of eq. (1), 0 <= d <= 1 */
+    uint64_t L;                 /* ring length in sites, L >= B, L % B == 0, L/B < 2^32 */
+    uint32_t stream_id;         /* Philox key word 1 */
+    int32_t init;               /* pcpd_init_kind */
+    const uint64_t *host_words; /* init == PCPD_INIT_HOST: planes*L words, plane-major,
+                                   natural site order; otherwise ignored */
+} pcpd_instance;
+
+/* Where the library puts its work. Every field may be 0 / NULL. */
+typedef struct {
+    void *hip_stream;      /* hipStream_t to enqueue on; NULL = the null stream */
+    void *dev_buf;         /* caller-owned device memory for the two lattice copies,
+                              at least pcpd_lattice_bytes() bytes, 256-byte aligned;
+                              NULL = the library allocates */
+    size_t dev_buf_bytes;
+} pcpd_device;
+
+/* Counts of one (instance, plane), summed over its 64 samples. */
+typedef struct {
+    uint64_t n;       /* occupied sites */
+    uint64_t n_pair;  /* pairs (j, j+1 mod L) with both sites occupied */
+    uint64_t alive;   /* bit b set iff sample b holds at least one particle */
+} pcpd_counts;
+
+/* Kernel shape of the sweep. Results never depend on it. */
+typedef struct {
+    uint32_t tile_cols;  /* blocks per workgroup tile including the halo; 0 = default */
+    uint32_t phase_max;  /* substeps run while a tile stays in LDS; 0 = default */
+} pcpd_tuning;
+
+typedef struct pcpd_ctx pcpd_ctx;
+
+/* Bytes of device memory for the two lattice copies of these instances
+ * (2 * 8 * planes * sum L). Validates like pcpd_init. */
+PCPD_API int pcpd_lattice_bytes(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+                       size_t *bytes_out);
+
+/* Create a context at Monte Carlo step t0 (t0 > 0 resumes a stored lattice:
+ * the lattice and t fully determine the future). Validation failures return
+ * PCPD_EINVAL before any device work and leave *out untouched. */
+PCPD_API int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
+              uint32_t n_inst, uint64_t t0, const pcpd_device *dev);
+
+/* Advance every instance by n_steps Monte Carlo steps (n_steps * B substeps).
+ * Asynchronous. PCPD_EOVERFLOW if (t + n_steps) * B leaves 64 bits. */
+PCPD_API int pcpd_sweep(pcpd_ctx *ctx, uint64_t n_steps);
+
+/* Counts of the current lattice into out[n_inst * planes] (instance-major).
+ * Synchronises. */
+PCPD_API int pcpd_density(pcpd_ctx *ctx, pcpd_counts *out);
+
+/* Sweep to each of the strictly increasing times[0..n_times) (each >= the
+ * current t) and record the counts there: out[r * n_inst * planes + i * planes + q].
+ * Synchronises once at the end. */
+PCPD_API int pcpd_run(pcpd_ctx *ctx, const uint64_t *times, uint32_t n_times, pcpd_counts *out);
+
+/* Copy instance `inst`'s planes*L words (plane-major, natural order) to or
+ * from the host. Synchronous. */
+PCPD_API int pcpd_get_lattice(pcpd_ctx *ctx, uint32_t inst, uint64_t *host_words);
+PCPD_API int pcpd_set_lattice(pcpd_ctx *ctx, uint32_t inst, const uint64_t *host_words);
+
+/* Current Monte Carlo step. */
+PCPD_API int pcpd_time(pcpd_ctx *ctx, uint64_t *t_out);
+
+/* Wait for enqueued work and report its errors. */
+PCPD_API int pcpd_sync(pcpd_ctx *ctx);
+
+/* Set or read the kernel shape (see pcpd_tuning). PCPD_EINVAL if the shape
+ * does not fit the device (LDS) or the block width. */
+PCPD_API int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning);
+PCPD_API int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning);
+
+/* Release the context and everything the library allocated for it. */
+PCPD_API int pcpd_free(pcpd_ctx *ctx);
+
+/* Static description of a status code. */
+PCPD_API const char *pcpd_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCPD_H */

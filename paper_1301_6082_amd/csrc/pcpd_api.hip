@@ -1,0 +1,468 @@
+// pcpd_api.hip -- host runtime behind include/pcpd.h: argument validation,
+// thresholds, buffer ownership, tiling, phase planning and the C ABI.
+// Everything numeric runs in the kernels of sweep.hip; this file only plans
+// and enqueues.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pcpd.h"
+#include "pcpd_internal.h"
+
+using pcpd::Counts;
+using pcpd::DenChunk;
+using pcpd::LatDesc;
+using pcpd::PhaseShape;
+using pcpd::TileDesc;
+
+static_assert(sizeof(pcpd_counts) == sizeof(Counts), "count layout");
+
+struct pcpd_ctx {
+    int32_t n = 2;          // tuple size
+    uint32_t B = 64;
+    uint32_t planes = 1;
+    uint32_t seed = 0;
+    uint32_t n_inst = 0;
+    std::vector<uint64_t> L;         // per instance
+    std::vector<uint64_t> inst_base; // word offset of instance i's first plane
+    uint64_t total_words = 0;        // planes * sum L
+    uint32_t nlat = 0;               // n_inst * planes
+
+    hipStream_t stream = nullptr;
+    uint64_t *buf[2] = {nullptr, nullptr};
+    int cur = 0;                     // index of the copy holding the current lattice
+    bool owns_buf = false;
+
+    LatDesc *d_lats = nullptr;
+    TileDesc *d_tiles = nullptr;
+    uint32_t ntiles = 0;
+    DenChunk *d_chunks = nullptr;
+    uint32_t nchunks = 0;
+    Counts *d_counts = nullptr;      // [count_slots][nlat]
+    uint32_t count_slots = 0;
+    Counts *h_counts = nullptr;      // pinned mirror of d_counts
+
+    std::vector<LatDesc> lats;       // host copy of d_lats
+    PhaseShape shape{};
+    uint32_t phase_max = 64;
+
+    uint64_t t = 0;
+    bool broken = false;
+};
+
+namespace {
+
+constexpr uint32_t kDenChunkWords = 8192;
+
+// K = rint(q * 2^34): the integer threshold of a probability-q decision.
+// ldexp is exact and rint rounds half to even.
+uint64_t rate_threshold(double q) { return static_cast<uint64_t>(std::rint(std::ldexp(q, 34))); }
+
+bool rate_ok(double q) { return std::isfinite(q) && q >= 0.0 && q <= 1.0; }
+
+int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst) {
+    if (!cfg || !inst || n_inst == 0) return PCPD_EINVAL;
+    if (cfg->model < 1 || cfg->model > 3) return PCPD_EINVAL;
+    const uint32_t n = static_cast<uint32_t>(cfg->model);
+    if (cfg->B < n + 2 || cfg->planes == 0 || cfg->planes >= (1u << 29)) return PCPD_EINVAL;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const pcpd_instance &in = inst[i];
+        if (!rate_ok(in.p) || !rate_ok(in.d)) return PCPD_EINVAL;
+        if (in.L < cfg->B || in.L % cfg->B != 0) return PCPD_EINVAL;
+        if (in.L / cfg->B >= (1ull << 32)) return PCPD_EINVAL;
+        if (in.init < PCPD_INIT_FULL || in.init > PCPD_INIT_HOST) return PCPD_EINVAL;
+        if (in.init == PCPD_INIT_HOST && !in.host_words) return PCPD_EINVAL;
+        const uint64_t words = in.L * cfg->planes;
+        if (words / cfg->planes != in.L || total + words < total) return PCPD_EINVAL;
+        total += words;
+    }
+    if (total > (1ull << 58)) return PCPD_EINVAL;
+    return PCPD_OK;
+}
+
+// Shape for `cols` LDS columns; hb halo blocks are needed for phase_max
+// substeps: an attempt reaches n+1 sites, so S substeps need (n+1)*S sites.
+bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, PhaseShape *out) {
+    if (cols == 0 || phase_max == 0) return false;
+    const uint64_t reach = static_cast<uint64_t>(n + 1) * phase_max;
+    const uint64_t hb = (reach + B - 1) / B;
+    if (cols <= 2 * hb) return false;
+    if (cols > 256) return false;
+    uint32_t ldw = cols | 1u;
+    if (pcpd::phase_lds_bytes(B, ldw) > pcpd::kMaxLdsBytes) return false;
+    out->cols = cols;
+    out->threads = (cols + 63u) / 64u * 64u;
+    out->ldw = ldw;
+    out->hb = static_cast<uint32_t>(hb);
+    return true;
+}
+
+// Default shape: the widest tile that fits LDS, one window per lane, and a
+// phase of one Monte Carlo step when B is small enough.
+bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_max) {
+    uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(B, 64));
+    for (; pm >= 1; pm = pm / 2) {
+        for (uint32_t cols = 256; cols >= 1; --cols) {
+            if (make_shape(n, B, cols, pm, shape)) {
+                *phase_max = pm;
+                return true;
+            }
+        }
+        if (pm == 1) break;
+    }
+    return false;
+}
+
+int fail(pcpd_ctx *ctx, hipError_t e) {
+    if (e == hipSuccess) return PCPD_OK;
+    if (ctx) ctx->broken = true;
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PCPD_ENOMEM
+                                                                       : PCPD_EDEVICE;
+}
+
+hipError_t build_tiles(pcpd_ctx *ctx) {
+    std::vector<TileDesc> tiles;
+    const uint32_t kmax = ctx->shape.cols - 2 * ctx->shape.hb;
+    for (uint32_t l = 0; l < ctx->nlat; ++l) {
+        const uint32_t nb = ctx->lats[l].nblocks;
+        for (uint32_t k0 = 0; k0 < nb; k0 += kmax) {
+            TileDesc td{};
+            td.lat = l;
+            td.k0 = k0;
+            td.kint = std::min(kmax, nb - k0);
+            tiles.push_back(td);
+        }
+    }
+    if (ctx->d_tiles) {
+        hipError_t e = hipFree(ctx->d_tiles);
+        ctx->d_tiles = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&ctx->d_tiles, tiles.size() * sizeof(TileDesc));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(ctx->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
+                  hipMemcpyHostToDevice);
+    ctx->ntiles = static_cast<uint32_t>(tiles.size());
+    return e;
+}
+
+hipError_t ensure_count_slots(pcpd_ctx *ctx, uint32_t slots) {
+    if (slots <= ctx->count_slots) return hipSuccess;
+    if (ctx->d_counts) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return e;
+        (void)hipFree(ctx->d_counts);
+        (void)hipHostFree(ctx->h_counts);
+        ctx->d_counts = nullptr;
+        ctx->h_counts = nullptr;
+        ctx->count_slots = 0;
+    }
+    const size_t bytes = static_cast<size_t>(slots) * ctx->nlat * sizeof(Counts);
+    hipError_t e = hipMalloc(&ctx->d_counts, bytes);
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc(&ctx->h_counts, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    ctx->count_slots = slots;
+    return hipSuccess;
+}
+
+// Enqueue n_steps Monte Carlo steps as phases of at most phase_max substeps.
+hipError_t enqueue_sweep(pcpd_ctx *ctx, uint64_t n_steps) {
+    uint64_t sub = ctx->t * ctx->B;
+    const uint64_t end = (ctx->t + n_steps) * ctx->B;
+    while (sub < end) {
+        const uint32_t S = static_cast<uint32_t>(std::min<uint64_t>(ctx->phase_max, end - sub));
+        hipError_t e = pcpd::launch_phase(ctx->n, ctx->buf[ctx->cur], ctx->buf[ctx->cur ^ 1],
+                                          ctx->d_lats, ctx->d_tiles, ctx->ntiles, sub, S, ctx->B,
+                                          ctx->shape, ctx->stream);
+        if (e != hipSuccess) return e;
+        ctx->cur ^= 1;
+        sub += S;
+    }
+    ctx->t += n_steps;
+    return hipSuccess;
+}
+
+hipError_t enqueue_density(pcpd_ctx *ctx, uint32_t slot) {
+    return pcpd::launch_density(ctx->buf[ctx->cur], ctx->d_lats, ctx->d_chunks, ctx->nchunks,
+                                ctx->d_counts + static_cast<size_t>(slot) * ctx->nlat, ctx->nlat,
+                                ctx->stream);
+}
+
+void release(pcpd_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->owns_buf && ctx->buf[0]) (void)hipFree(ctx->buf[0]);
+    if (ctx->d_lats) (void)hipFree(ctx->d_lats);
+    if (ctx->d_tiles) (void)hipFree(ctx->d_tiles);
+    if (ctx->d_chunks) (void)hipFree(ctx->d_chunks);
+    if (ctx->d_counts) (void)hipFree(ctx->d_counts);
+    if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
+    delete ctx;
+}
+
+bool overflow_steps(uint64_t t, uint64_t steps, uint32_t B) {
+    if (t + steps < t) return true;
+    const uint64_t T = t + steps;
+    return T > UINT64_MAX / B;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcpd_lattice_bytes(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+                       size_t *bytes_out) {
+    int v = validate(cfg, inst, n_inst);
+    if (v != PCPD_OK) return v;
+    if (!bytes_out) return PCPD_EINVAL;
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) total += inst[i].L * cfg->planes;
+    *bytes_out = static_cast<size_t>(2 * total * sizeof(uint64_t));
+    return PCPD_OK;
+}
+
+int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
+              uint32_t n_inst, uint64_t t0, const pcpd_device *dev) {
+    if (!out) return PCPD_EINVAL;
+    int v = validate(cfg, inst, n_inst);
+    if (v != PCPD_OK) return v;
+    if (overflow_steps(t0, 0, cfg->B)) return PCPD_EOVERFLOW;
+    size_t need = 0;
+    pcpd_lattice_bytes(cfg, inst, n_inst, &need);
+    if (dev && dev->dev_buf) {
+        if (dev->dev_buf_bytes < need) return PCPD_EINVAL;
+        if (reinterpret_cast<uintptr_t>(dev->dev_buf) % 256 != 0) return PCPD_EINVAL;
+    }
+    PhaseShape shape{};
+    uint32_t pmax = 0;
+    if (!default_shape(static_cast<uint32_t>(cfg->model), cfg->B, &shape, &pmax))
+        return PCPD_EINVAL;
+
+    pcpd_ctx *ctx = new (std::nothrow) pcpd_ctx();
+    if (!ctx) return PCPD_ENOMEM;
+    ctx->n = cfg->model;
+    ctx->B = cfg->B;
+    ctx->planes = cfg->planes;
+    ctx->seed = cfg->seed;
+    ctx->n_inst = n_inst;
+    ctx->nlat = n_inst * cfg->planes;
+    ctx->t = t0;
+    ctx->shape = shape;
+    ctx->phase_max = pmax;
+    ctx->stream = dev ? static_cast<hipStream_t>(dev->hip_stream) : nullptr;
+
+    uint64_t base = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        ctx->L.push_back(inst[i].L);
+        ctx->inst_base.push_back(base);
+        const uint64_t kd = rate_threshold(inst[i].d), kp = rate_threshold(inst[i].p);
+        for (uint32_t q = 0; q < cfg->planes; ++q) {
+            LatDesc ld{};
+            ld.base = base + q * inst[i].L;
+            ld.L = inst[i].L;
+            ld.nblocks = static_cast<uint32_t>(inst[i].L / cfg->B);
+            ld.plane = q;
+            ld.key0 = cfg->seed;
+            ld.key1 = inst[i].stream_id;
+            ld.kd_hi = static_cast<uint32_t>(kd >> 32);
+            ld.kd_lo = static_cast<uint32_t>(kd);
+            ld.kp_hi = static_cast<uint32_t>(kp >> 32);
+            ld.kp_lo = static_cast<uint32_t>(kp);
+            ctx->lats.push_back(ld);
+        }
+        base += inst[i].L * cfg->planes;
+    }
+    ctx->total_words = base;
+
+    hipError_t e = hipSuccess;
+    if (dev && dev->dev_buf) {
+        ctx->buf[0] = static_cast<uint64_t *>(dev->dev_buf);
+        ctx->owns_buf = false;
+    } else {
+        void *p = nullptr;
+        e = hipMalloc(&p, need);
+        if (e != hipSuccess) {
+            release(ctx);
+            return fail(nullptr, e);
+        }
+        ctx->buf[0] = static_cast<uint64_t *>(p);
+        ctx->owns_buf = true;
+    }
+    ctx->buf[1] = ctx->buf[0] + ctx->total_words;
+
+    // density chunks
+    std::vector<DenChunk> chunks;
+    for (uint32_t l = 0; l < ctx->nlat; ++l) {
+        for (uint64_t w0 = 0; w0 < ctx->lats[l].L; w0 += kDenChunkWords) {
+            DenChunk c{};
+            c.lat = l;
+            c.w0 = w0;
+            c.nw = static_cast<uint32_t>(std::min<uint64_t>(kDenChunkWords, ctx->lats[l].L - w0));
+            chunks.push_back(c);
+        }
+    }
+    ctx->nchunks = static_cast<uint32_t>(chunks.size());
+
+    if ((e = hipMalloc(&ctx->d_lats, ctx->lats.size() * sizeof(LatDesc))) != hipSuccess ||
+        (e = hipMemcpy(ctx->d_lats, ctx->lats.data(), ctx->lats.size() * sizeof(LatDesc),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMalloc(&ctx->d_chunks, chunks.size() * sizeof(DenChunk))) != hipSuccess ||
+        (e = hipMemcpy(ctx->d_chunks, chunks.data(), chunks.size() * sizeof(DenChunk),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = build_tiles(ctx)) != hipSuccess || (e = ensure_count_slots(ctx, 1)) != hipSuccess) {
+        release(ctx);
+        return fail(nullptr, e);
+    }
+
+    // initial lattice into copy 0
+    for (uint32_t i = 0; i < n_inst && e == hipSuccess; ++i) {
+        uint64_t *dst = ctx->buf[0] + ctx->inst_base[i];
+        const uint64_t words = inst[i].L * cfg->planes;
+        if (inst[i].init == PCPD_INIT_HOST)
+            e = hipMemcpyAsync(dst, inst[i].host_words, words * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, ctx->stream);
+        else
+            e = pcpd::launch_fill(dst, words, inst[i].init == PCPD_INIT_FULL ? ~0ull : 0ull,
+                                  ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        release(ctx);
+        return fail(nullptr, e);
+    }
+    ctx->cur = 0;
+    *out = ctx;
+    return PCPD_OK;
+}
+
+int pcpd_sweep(pcpd_ctx *ctx, uint64_t n_steps) {
+    if (!ctx) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    if (overflow_steps(ctx->t, n_steps, ctx->B)) return PCPD_EOVERFLOW;
+    return fail(ctx, enqueue_sweep(ctx, n_steps));
+}
+
+int pcpd_density(pcpd_ctx *ctx, pcpd_counts *out) {
+    if (!ctx || !out) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    hipError_t e = enqueue_density(ctx, 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts, ctx->nlat * sizeof(Counts),
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    std::memcpy(out, ctx->h_counts, ctx->nlat * sizeof(Counts));
+    return PCPD_OK;
+}
+
+int pcpd_run(pcpd_ctx *ctx, const uint64_t *times, uint32_t n_times, pcpd_counts *out) {
+    if (!ctx || (!times && n_times) || (!out && n_times)) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    for (uint32_t r = 0; r < n_times; ++r) {
+        if (times[r] < ctx->t || (r > 0 && times[r] <= times[r - 1])) return PCPD_EINVAL;
+    }
+    if (n_times && overflow_steps(times[n_times - 1], 0, ctx->B)) return PCPD_EOVERFLOW;
+    hipError_t e = ensure_count_slots(ctx, n_times);
+    for (uint32_t r = 0; r < n_times && e == hipSuccess; ++r) {
+        e = enqueue_sweep(ctx, times[r] - ctx->t);
+        if (e == hipSuccess) e = enqueue_density(ctx, r);
+    }
+    if (e == hipSuccess && n_times)
+        e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts,
+                           static_cast<size_t>(n_times) * ctx->nlat * sizeof(Counts),
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    if (n_times)
+        std::memcpy(out, ctx->h_counts, static_cast<size_t>(n_times) * ctx->nlat * sizeof(Counts));
+    return PCPD_OK;
+}
+
+int pcpd_get_lattice(pcpd_ctx *ctx, uint32_t inst, uint64_t *host_words) {
+    if (!ctx || !host_words || inst >= ctx->n_inst) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    const size_t bytes = ctx->L[inst] * ctx->planes * sizeof(uint64_t);
+    hipError_t e = hipMemcpyAsync(host_words, ctx->buf[ctx->cur] + ctx->inst_base[inst], bytes,
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return fail(ctx, e);
+}
+
+int pcpd_set_lattice(pcpd_ctx *ctx, uint32_t inst, const uint64_t *host_words) {
+    if (!ctx || !host_words || inst >= ctx->n_inst) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    const size_t bytes = ctx->L[inst] * ctx->planes * sizeof(uint64_t);
+    hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur] + ctx->inst_base[inst], host_words, bytes,
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return fail(ctx, e);
+}
+
+int pcpd_time(pcpd_ctx *ctx, uint64_t *t_out) {
+    if (!ctx || !t_out) return PCPD_EINVAL;
+    *t_out = ctx->t;
+    return PCPD_OK;
+}
+
+int pcpd_sync(pcpd_ctx *ctx) {
+    if (!ctx) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    return fail(ctx, hipStreamSynchronize(ctx->stream));
+}
+
+int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning) {
+    if (!ctx || !tuning) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    PhaseShape shape{};
+    uint32_t pmax = ctx->phase_max;
+    if (tuning->tile_cols == 0 && tuning->phase_max == 0) {
+        if (!default_shape(static_cast<uint32_t>(ctx->n), ctx->B, &shape, &pmax))
+            return PCPD_EINVAL;
+    } else {
+        pmax = tuning->phase_max ? tuning->phase_max : ctx->phase_max;
+        const uint32_t cols = tuning->tile_cols ? tuning->tile_cols : ctx->shape.cols;
+        if (!make_shape(static_cast<uint32_t>(ctx->n), ctx->B, cols, pmax, &shape))
+            return PCPD_EINVAL;
+    }
+    // tiles in flight must not see their table change
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    ctx->shape = shape;
+    ctx->phase_max = pmax;
+    return fail(ctx, build_tiles(ctx));
+}
+
+int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
+    if (!ctx || !tuning) return PCPD_EINVAL;
+    tuning->tile_cols = ctx->shape.cols;
+    tuning->phase_max = ctx->phase_max;
+    return PCPD_OK;
+}
+
+int pcpd_free(pcpd_ctx *ctx) {
+    if (!ctx) return PCPD_EINVAL;
+    release(ctx);
+    return PCPD_OK;
+}
+
+const char *pcpd_strerror(int status) {
+    switch (status) {
+        case PCPD_OK: return "success";
+        case PCPD_EINVAL: return "invalid argument";
+        case PCPD_ENOMEM: return "out of memory";
+        case PCPD_EDEVICE: return "device error";
+        case PCPD_ESTATE: return "context unusable after an earlier device error";
+        case PCPD_EOVERFLOW: return "substep counter overflow";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

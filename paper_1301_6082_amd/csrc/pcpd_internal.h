@@ -1,0 +1,71 @@
+// pcpd_internal.h -- device-side tables and kernel launchers shared by the
+// two translation units of libpcpd (kernels in sweep.hip, host runtime in
+// pcpd_api.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pcpd {
+
+// One (instance, plane): a ring of nblocks*B words at word offset `base` of
+// each lattice copy. 48 bytes, read once per workgroup into SGPRs.
+struct LatDesc {
+    uint64_t base;     // word offset of site 0
+    uint64_t L;        // sites (words) in the ring
+    uint32_t nblocks;  // L / B
+    uint32_t plane;    // plane index q: Philox counter word 1 is 8q + draw
+    uint32_t key0;     // Philox key word 0 (seed)
+    uint32_t key1;     // Philox key word 1 (stream id)
+    uint32_t kd_hi;    // diffusion threshold K_d = kd_hi * 2^32 + kd_lo
+    uint32_t kd_lo;
+    uint32_t kp_hi;    // annihilation threshold K_p
+    uint32_t kp_lo;
+};
+
+// One workgroup's tile: interior blocks [k0, k0 + kint) of lattice `lat`.
+struct TileDesc {
+    uint32_t lat;
+    uint32_t k0;
+    uint32_t kint;
+    uint32_t pad;
+};
+
+// One workgroup's share of a density reduction: words [w0, w0 + nw) of `lat`.
+struct DenChunk {
+    uint32_t lat;
+    uint32_t nw;
+    uint64_t w0;
+};
+
+// Counts of one (instance, plane); layout identical to pcpd_counts.
+struct Counts {
+    unsigned long long n;
+    unsigned long long n_pair;
+    unsigned long long alive;
+};
+
+// Largest LDS allocation of one workgroup on gfx950.
+constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
+
+// Kernel shape of one phase launch.
+struct PhaseShape {
+    uint32_t cols;     // blocks held in LDS per workgroup (interior + 2*halo)
+    uint32_t threads;  // workgroup size (multiple of 64, >= cols)
+    uint32_t ldw;      // LDS row pitch in words (>= cols, odd)
+    uint32_t hb;       // halo blocks on each side
+};
+
+hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                        const TileDesc *tiles, uint32_t ntiles, uint64_t s0, uint32_t S,
+                        uint32_t B, const PhaseShape &shape, hipStream_t stream);
+
+hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream_t stream);
+
+hipError_t launch_density(const uint64_t *buf, const LatDesc *lats, const DenChunk *chunks,
+                          uint32_t nchunks, Counts *out, uint32_t nlat, hipStream_t stream);
+
+size_t phase_lds_bytes(uint32_t B, uint32_t ldw);
+
+}  // namespace pcpd

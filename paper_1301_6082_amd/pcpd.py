@@ -1,0 +1,223 @@
+"""ctypes binding of libpcpd (include/pcpd.h). Argument marshalling only:
+every step of the sweep runs in the library's HIP kernels.
+
+PyTorch supplies device memory (the two lattice copies are one torch tensor)
+and the stream (torch's current stream); it is imported before the library so
+that both share one HIP runtime. There is no fallback: if libpcpd.so is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpcpd.so")
+
+PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
+DP, PCPD, TCPD = 1, 2, 3
+INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
+
+u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("model", i32), ("B", u32), ("planes", u32), ("seed", u32)]
+
+
+class InstanceC(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("d", ctypes.c_double), ("L", u64),
+                ("stream_id", u32), ("init", i32), ("host_words", ctypes.POINTER(u64))]
+
+
+class Device(ctypes.Structure):
+    _fields_ = [("hip_stream", ctypes.c_void_p), ("dev_buf", ctypes.c_void_p),
+                ("dev_buf_bytes", ctypes.c_size_t)]
+
+
+class CountsC(ctypes.Structure):
+    _fields_ = [("n", u64), ("n_pair", u64), ("alive", u64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_cols", u32), ("phase_max", u32)]
+
+
+EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcpd_run",
+           "pcpd_get_lattice", "pcpd_set_lattice", "pcpd_time", "pcpd_sync",
+           "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_free", "pcpd_strerror"]
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"libpcpd.so not built ({path}); run python -m paper_1301_6082_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "pcpd_lattice_bytes": ([P(Config), P(InstanceC), u32, P(ctypes.c_size_t)], ctypes.c_int),
+        "pcpd_init": ([P(vp), P(Config), P(InstanceC), u32, u64, P(Device)], ctypes.c_int),
+        "pcpd_sweep": ([vp, u64], ctypes.c_int),
+        "pcpd_density": ([vp, P(CountsC)], ctypes.c_int),
+        "pcpd_run": ([vp, P(u64), u32, P(CountsC)], ctypes.c_int),
+        "pcpd_get_lattice": ([vp, u32, P(u64)], ctypes.c_int),
+        "pcpd_set_lattice": ([vp, u32, P(u64)], ctypes.c_int),
+        "pcpd_time": ([vp, P(u64)], ctypes.c_int),
+        "pcpd_sync": ([vp], ctypes.c_int),
+        "pcpd_set_tuning": ([vp, P(Tuning)], ctypes.c_int),
+        "pcpd_get_tuning": ([vp, P(Tuning)], ctypes.c_int),
+        "pcpd_free": ([vp], ctypes.c_int),
+        "pcpd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+class PcpdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.pcpd_strerror(status).decode()} ({status})")
+
+
+def _check(status: int, where: str):
+    if status != PCPD_OK:
+        raise PcpdError(status, where)
+
+
+def _u64p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(u64))
+
+
+def _instances(insts, planes):
+    arr = (InstanceC * len(insts))()
+    keep = []
+    for i, it in enumerate(insts):
+        arr[i].p = float(it.p)
+        arr[i].d = float(it.d)
+        arr[i].L = int(it.L)
+        arr[i].stream_id = int(it.stream_id)
+        arr[i].init = int(it.init)
+        if int(it.init) == INIT_HOST:
+            w = np.ascontiguousarray(np.asarray(it.host_words, dtype=np.uint64))
+            if w.shape != (planes * int(it.L),):
+                raise ValueError("host_words must hold planes*L words")
+            keep.append(w)
+            arr[i].host_words = _u64p(w)
+        else:
+            arr[i].host_words = None
+    return arr, keep
+
+
+def lattice_bytes(model: int, B: int, planes: int, seed: int, instances) -> int:
+    cfg = Config(int(model), int(B), int(planes), int(seed))
+    arr, _ = _instances(instances, planes)
+    out = ctypes.c_size_t()
+    _check(_lib.pcpd_lattice_bytes(ctypes.byref(cfg), arr, len(instances), ctypes.byref(out)),
+           "pcpd_lattice_bytes")
+    return int(out.value)
+
+
+class Sim:
+    """A context of one or more instances (workloads.Instance-like objects with
+    p, d, L, stream_id, init, host_words) sharing model, B, planes and seed."""
+
+    def __init__(self, model: int, B: int, planes: int, seed: int, instances, t0: int = 0,
+                 device: int | None = None, torch_buffer: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpcpd needs a ROCm GPU; none is visible")
+        self.model, self.B, self.planes, self.seed = int(model), int(B), int(planes), int(seed)
+        self.instances = list(instances)
+        self.n_inst = len(self.instances)
+        self.Ls = [int(i.L) for i in self.instances]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        cfg = Config(self.model, self.B, self.planes, self.seed)
+        arr, keep = _instances(self.instances, self.planes)
+        dev = Device()
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            dev.hip_stream = ctypes.c_void_p(self.stream.cuda_stream)
+            self._buf = None
+            if torch_buffer:
+                nbytes = lattice_bytes(self.model, self.B, self.planes, self.seed, self.instances)
+                self._buf = torch.empty(nbytes // 8, dtype=torch.int64, device=self.device)
+                dev.dev_buf = ctypes.c_void_p(self._buf.data_ptr())
+                dev.dev_buf_bytes = nbytes
+            self._ctx = ctypes.c_void_p()
+            _check(_lib.pcpd_init(ctypes.byref(self._ctx), ctypes.byref(cfg), arr, self.n_inst,
+                                  int(t0), ctypes.byref(dev)), "pcpd_init")
+        del keep
+
+    # -- stepping and observables
+    def sweep(self, n_steps: int):
+        _check(_lib.pcpd_sweep(self._ctx, int(n_steps)), "pcpd_sweep")
+
+    def sync(self):
+        _check(_lib.pcpd_sync(self._ctx), "pcpd_sync")
+
+    def density(self) -> np.ndarray:
+        """uint64 [n_inst, planes, 3] = (N, N_pair, alive)."""
+        out = (CountsC * (self.n_inst * self.planes))()
+        _check(_lib.pcpd_density(self._ctx, out), "pcpd_density")
+        return np.frombuffer(out, dtype=np.uint64).reshape(self.n_inst, self.planes, 3).copy()
+
+    def run(self, times: Sequence[int]) -> np.ndarray:
+        """uint64 [n_times, n_inst, planes, 3] at each record time."""
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
+        out = (CountsC * (len(t) * self.n_inst * self.planes))()
+        _check(_lib.pcpd_run(self._ctx, _u64p(t), len(t), out), "pcpd_run")
+        return np.frombuffer(out, dtype=np.uint64).reshape(len(t), self.n_inst, self.planes, 3).copy()
+
+    # -- state
+    def get_lattice(self, inst: int) -> np.ndarray:
+        w = np.empty(self.planes * self.Ls[inst], dtype=np.uint64)
+        _check(_lib.pcpd_get_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_get_lattice")
+        return w
+
+    def set_lattice(self, inst: int, words) -> None:
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+        if w.shape != (self.planes * self.Ls[inst],):
+            raise ValueError("set_lattice needs planes*L words")
+        _check(_lib.pcpd_set_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_set_lattice")
+
+    @property
+    def time(self) -> int:
+        t = u64()
+        _check(_lib.pcpd_time(self._ctx, ctypes.byref(t)), "pcpd_time")
+        return int(t.value)
+
+    def set_tuning(self, tile_cols: int = 0, phase_max: int = 0):
+        tu = Tuning(int(tile_cols), int(phase_max))
+        _check(_lib.pcpd_set_tuning(self._ctx, ctypes.byref(tu)), "pcpd_set_tuning")
+
+    def get_tuning(self):
+        tu = Tuning()
+        _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
+        return int(tu.tile_cols), int(tu.phase_max)
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            _lib.pcpd_free(self._ctx)
+            self._ctx = ctypes.c_void_p()
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP sweep (through the C ABI) against the CPU oracle,
+bit-exact on lattice words and on every recorded count."""
+import numpy as np
+import pytest
+
+from paper_1301_6082_amd import workloads as wl
+from paper_1301_6082_amd.workloads import Instance
+
+from gpu_common import aggregate_counts, oracle_runs, per_sample_counts
+
+pytestmark = pytest.mark.gpu
+
+FULL = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def pcpd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_6082_amd import pcpd as mod
+    return mod
+
+
+def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t0=0):
+    """GPU run with records at `times` vs the oracle on every plane, all samples."""
+    print(f"[parity] model={model} B={B} planes={planes} n_inst={len(instances)} "
+          f"L={[i.L for i in instances]} times={times[:4]}..{times[-1]} tuning={tuning}",
+          flush=True)
+    with pcpd.Sim(model, B, planes, seed, instances, t0=t0) as sim:
+        if tuning:
+            sim.set_tuning(*tuning)
+        counts = sim.run(times)
+        lat = [sim.get_lattice(i) for i in range(len(instances))]
+    keys, runs = oracle_runs(model, B, planes, seed, instances, times, t0=t0)
+    for (i, q), r in zip(keys, runs):
+        L = instances[i].L
+        np.testing.assert_array_equal(lat[i][q * L:(q + 1) * L], r.words,
+                                      err_msg=f"lattice inst {i} plane {q}")
+        N, NP, alive = r.counts()
+        np.testing.assert_array_equal(counts[:, i, q, 0], N, err_msg=f"N inst {i} plane {q}")
+        np.testing.assert_array_equal(counts[:, i, q, 1], NP, err_msg=f"Npair inst {i} plane {q}")
+        np.testing.assert_array_equal(counts[:, i, q, 2], alive, err_msg=f"alive {i} {q}")
+    return counts, lat
+
+
+def test_cfg1_full_parity(pcpd):
+    """PCPD ring L=1024, d=0.5, p=0.1, 1000 MC steps, all 100 records."""
+    c = wl.cfg1()
+    counts, _ = _compare_full(pcpd, c.model, c.B, c.planes, c.seed, c.instances,
+                              [0] + c.times)
+    assert counts[0, 0, 0, 0] == 64 * 1024
+
+
+def test_several_tiles_and_ragged_tail(pcpd):
+    # 537 blocks: two full 250-block tiles and a ragged 37-block tile per plane
+    insts = [Instance(0.13, 0.3, 64 * 537, 0), Instance(0.2, 0.7, 64 * 300, 5)]
+    _compare_full(pcpd, 2, 64, 2, 7, insts, [0, 1, 3, 12])
+
+
+@pytest.mark.parametrize("model", [1, 3])
+def test_dp_and_tcpd_parity(pcpd, model):
+    insts = [Instance(0.08, 0.5, 64 * 260, 1), Instance(0.3, 0.1, 64 * 17, 2)]
+    _compare_full(pcpd, model, 64, 1, 3, insts, [2, 9])
+
+
+@pytest.mark.parametrize("tuning", [(256, 64), (128, 64), (64, 16), (9, 1), (40, 7), (200, 33)])
+def test_tile_shape_does_not_change_results(pcpd, tuning):
+    insts = [Instance(0.12, 0.4, 64 * 301, 3)]
+    _compare_full(pcpd, 2, 64, 1, 11, insts, [4], tuning=tuning)
+
+
+@pytest.mark.parametrize("L,B,model", [(4, 4, 2), (5, 5, 2), (8, 4, 2), (6, 6, 3), (3, 3, 1),
+                                       (192, 192, 2), (96, 32, 2), (1000, 8, 2)])
+def test_small_rings_and_block_widths(pcpd, L, B, model):
+    insts = [Instance(0.2, 0.3, L, 0), Instance(0.05, 0.9, L, 1)]
+    _compare_full(pcpd, model, B, 2, 1, insts, [1, 2, 17])
+
+
+def test_host_init_resume_and_chunking(pcpd):
+    L = 64 * 40
+    start = wl.random_lattice(L, 2, 0.4, 21)
+    insts = [Instance(0.1, 0.25, L, 4, wl.INIT_HOST, start)]
+    # one run to 30 vs 7 + 23 via a stored lattice and t0 = 7
+    with pcpd.Sim(2, 64, 2, 5, insts) as sim:
+        sim.sweep(7)
+        mid = sim.get_lattice(0)
+        assert sim.time == 7
+        sim.sweep(10)
+        sim.sweep(13)
+        end = sim.get_lattice(0)
+    resumed = [Instance(0.1, 0.25, L, 4, wl.INIT_HOST, mid)]
+    with pcpd.Sim(2, 64, 2, 5, resumed, t0=7) as sim:
+        sim.sweep(23)
+        end2 = sim.get_lattice(0)
+        dens = sim.density()
+    np.testing.assert_array_equal(end, end2)
+    keys, runs = oracle_runs(2, 64, 2, 5, insts, [30])
+    for (i, q), r in zip(keys, runs):
+        np.testing.assert_array_equal(end[q * L:(q + 1) * L], r.words)
+        N, NP, alive = r.counts()
+        assert (dens[0, q] == [N[0], NP[0], alive[0]]).all()
+
+
+def test_set_lattice_then_sweep(pcpd):
+    L = 64 * 20
+    a = wl.random_lattice(L, 1, 0.5, 3)
+    insts = [Instance(0.15, 0.5, L, 0)]
+    with pcpd.Sim(2, 64, 1, 9, insts) as sim:
+        sim.set_lattice(0, a)
+        np.testing.assert_array_equal(sim.get_lattice(0), a)
+        sim.sweep(5)
+        got = sim.get_lattice(0)
+    host = [Instance(0.15, 0.5, L, 0, wl.INIT_HOST, a)]
+    _, runs = oracle_runs(2, 64, 1, 9, host, [5])
+    np.testing.assert_array_equal(got, runs[0].words)
+
+
+def test_empty_and_absorbing(pcpd):
+    insts = [Instance(0.1, 0.5, 64 * 10, 0, wl.INIT_EMPTY)]
+    with pcpd.Sim(2, 64, 1, 1, insts) as sim:
+        c = sim.run([0, 5, 50])
+        assert (c == 0).all()
+        assert (sim.get_lattice(0) == 0).all()
+
+
+def test_density_kernel_matches_lattice(pcpd):
+    L = 64 * 700
+    insts = [Instance(0.11, 0.2, L, 0, wl.INIT_HOST, wl.random_lattice(L, 3, 0.3, 8))]
+    with pcpd.Sim(2, 64, 3, 1, insts) as sim:
+        sim.sweep(3)
+        dens = sim.density()
+        words = sim.get_lattice(0)
+    for q in range(3):
+        assert tuple(int(x) for x in dens[0, q]) == aggregate_counts(words[q * L:(q + 1) * L])
+
+
+def test_cfg2_full_size_sampled(pcpd):
+    """The full PCPD L=2^20, 4-plane, 16-p workload in the benchmark's launch
+    shape, 8 MC steps with records at t = 1..8; sampled (instance, plane,
+    sample) trajectories against the oracle, every site, every record, plus
+    count properties on all planes."""
+    c = wl.cfg2()
+    times = [1, 2, 3, 4, 5, 6, 7, 8]
+    picks = [(0, 0, 0), (5, 3, 17), (9, 1, 63), (15, 2, 40), (15, 0, 5), (11, 3, 31)]
+    snaps = {}
+    with pcpd.Sim(c.model, c.B, c.planes, c.seed, c.instances) as sim:
+        counts = sim.run([0])
+        assert (counts[0, :, :, 0] == 64 * (1 << 20)).all()
+        for t in times:
+            counts = sim.run([t])
+            for (i, q, b) in picks:
+                w = sim.get_lattice(i)[q << 20:(q + 1) << 20]
+                snaps[(i, q, b, t)] = (w >> np.uint64(b)) & np.uint64(1)
+            # properties of every plane
+            n, npair = counts[0, :, :, 0], counts[0, :, :, 1]
+            assert (npair <= n).all() and (n <= 64 * (1 << 20)).all()
+    which = [(i, q) for (i, q, _) in picks]
+    for k, (i, q, b) in enumerate(picks):
+        _, runs = oracle_runs(c.model, c.B, c.planes, c.seed, c.instances, times,
+                              samples=1 << b, which=[(i, q)])
+        r = runs[0]
+        final = (r.words >> np.uint64(b)) & np.uint64(1)
+        np.testing.assert_array_equal(snaps[(i, q, b, times[-1])], final,
+                                      err_msg=f"inst {i} plane {q} sample {b}")
+        for ti, t in enumerate(times):
+            bits = snaps[(i, q, b, t)].astype(np.int64)
+            assert bits.sum() == int(r.n[ti, b]), (i, q, b, t)
+            assert (bits & np.roll(bits, -1)).sum() == int(r.pair[ti, b]), (i, q, b, t)
+    assert len(which) == len(picks)
+
+
+def test_cfg4_tcpd_full_size_sampled(pcpd):
+    """TCPD ring L=2^18, 8 p values, 32 MC steps; one sample of every instance."""
+    c = wl.cfg4()
+    with pcpd.Sim(c.model, c.B, c.planes, c.seed, c.instances) as sim:
+        counts = sim.run([32])
+        lat = [sim.get_lattice(i) for i in range(len(c.instances))]
+    for i in range(len(c.instances)):
+        b = (7 * i + 3) % 64
+        _, runs = oracle_runs(c.model, c.B, 1, c.seed, c.instances, [32], samples=1 << b,
+                              which=[(i, 0)])
+        np.testing.assert_array_equal(lat[i] & np.uint64(1 << b), runs[0].words)
+        assert tuple(int(x) for x in counts[0, i, 0]) == aggregate_counts(lat[i])
+
+
+def test_cfg3_batch_sampled(pcpd):
+    """The 512-instance batch of uneven L in one context: sampled instances,
+    all 64 samples, against the oracle run alone."""
+    c = wl.cfg3()
+    times = [4, 16]
+    with pcpd.Sim(c.model, c.B, c.planes, c.seed, c.instances) as sim:
+        counts = sim.run(times)
+        Ls = np.array([i.L for i in c.instances])
+        picks = [int(np.argmin(Ls)), 7, 100, 255, 511]
+        lat = {i: sim.get_lattice(i) for i in picks}
+    for i in picks:
+        samples = FULL if Ls[i] <= 20000 else (1 << 3) | (1 << 60)
+        _, runs = oracle_runs(c.model, c.B, 1, c.seed, c.instances, times, samples=samples,
+                              which=[(i, 0)])
+        r = runs[0]
+        np.testing.assert_array_equal(lat[i] & np.uint64(samples), r.words, err_msg=f"inst {i}")
+        if samples == FULL:
+            N, NP, alive = r.counts()
+            np.testing.assert_array_equal(counts[:, i, 0, 0], N)
+            np.testing.assert_array_equal(counts[:, i, 0, 1], NP)
+            np.testing.assert_array_equal(counts[:, i, 0, 2], alive)
+        else:
+            n, pair = per_sample_counts(lat[i])
+            for b in (3, 60):
+                assert n[b] == r.n[-1, b] and pair[b] == r.pair[-1, b]
