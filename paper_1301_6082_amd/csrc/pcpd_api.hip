@@ -96,7 +96,7 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
     if (cols <= 2 * hb) return false;
     if (cols > 256) return false;
     uint32_t ldw = cols | 1u;
-    if (pcpd::phase_lds_bytes(B, ldw) > pcpd::kMaxLdsBytes) return false;
+    if (pcpd::phase_lds_bytes(B, ldw, phase_max) > pcpd::kMaxLdsBytes) return false;
     out->cols = cols;
     out->threads = (cols + 63u) / 64u * 64u;
     out->ldw = ldw;

@@ -66,6 +66,7 @@ hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream
 hipError_t launch_density(const uint64_t *buf, const LatDesc *lats, const DenChunk *chunks,
                           uint32_t nchunks, Counts *out, uint32_t nlat, hipStream_t stream);
 
-size_t phase_lds_bytes(uint32_t B, uint32_t ldw);
+// LDS of one phase workgroup: B x ldw lattice words and S local sites.
+size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S);
 
 }  // namespace pcpd

@@ -47,9 +47,10 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t ka, uint32_t kb) {
         const uint64_t pa = static_cast<uint64_t>(c.x) * kMulA;
         const uint64_t pb = static_cast<uint64_t>(c.z) * kMulB;
         U4 nx;
-        nx.x = static_cast<uint32_t>(pb >> 32) ^ c.y ^ ka;
+        // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+        nx.x = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c.y, ka, 0x96);
         nx.y = static_cast<uint32_t>(pb);
-        nx.z = static_cast<uint32_t>(pa >> 32) ^ c.w ^ kb;
+        nx.z = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c.w, kb, 0x96);
         nx.w = static_cast<uint32_t>(pa);
         c = nx;
         ka += kWeylA;
@@ -58,7 +59,7 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t ka, uint32_t kb) {
     return c;
 }
 
-// Local site of substep s (uniform across the workgroup: it runs on SALU).
+// Local site of substep s: o = floor(x0 * B / 2^32) of draw 7, window 0.
 __device__ __forceinline__ uint32_t substep_site(const LatDesc &ld, uint64_t s, uint32_t B) {
     const U4 x = philox10(U4{0u, (ld.plane << 3) | 7u, static_cast<uint32_t>(s),
                              static_cast<uint32_t>(s >> 32)},
@@ -66,56 +67,60 @@ __device__ __forceinline__ uint32_t substep_site(const LatDesc &ld, uint64_t s, 
     return static_cast<uint32_t>((static_cast<uint64_t>(x.x) * B) >> 32);
 }
 
-// Probability-q decision mask on one 32-bit half: sample b fires iff
-// (2*a_b + b_b) * 2^32 + g < kh * 2^32 + kl, a = X1 half, b = X2 half.
-// f_u is the outcome for prefix u = 2a + b: all-ones below kh, the shared
-// comparison g < kl at kh, zero above. Selecting f_u by the two bits takes
-// three bitfield inserts.
-struct Sel {
-    uint32_t f0, f1, f2, f3;
+// Truth table of a three-input bitwise function for v_bitop3_b32: bit
+// (4*a + 2*b + c) of the table is f(a, b, c). Evaluated on the canonical
+// operand patterns a = 0xF0, b = 0xCC, c = 0xAA.
+template <typename F>
+constexpr uint32_t lut3(F f) {
+    return f(0xF0u, 0xCCu, 0xAAu) & 0xFFu;
+}
+
+// Probability-q decision, one 32-bit half: sample bit fires iff
+// (2*a + b) * 2^32 + g < KH * 2^32 + kl, a = bit of X1, b = bit of X2,
+// t = all-ones iff the shared tail g < kl. For each integer part KH of the
+// threshold the decision is a fixed function of (a, b, t):
+//   KH=0: u == 0 and t;  KH=1: u == 0, or u == 1 and t;  KH=2: u <= 1, or u == 2 and t;
+//   KH=3: u <= 2, or t;  KH=4: always (q = 1).
+template <int KH>
+struct Decide {
+    static constexpr uint32_t lut() {
+        if constexpr (KH == 0) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a & ~b & t; });
+        else if constexpr (KH == 1) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a & (~b | t); });
+        else if constexpr (KH == 2) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a | (~b & t); });
+        else if constexpr (KH == 3) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a | ~b | t; });
+        else return 0xFFu;
+    }
+    __device__ static __forceinline__ uint32_t half(uint32_t a, uint32_t b, uint32_t t) {
+        if constexpr (KH >= 4) return 0xFFFFFFFFu;
+        else return __builtin_amdgcn_bitop3_b32(a, b, t, lut());
+    }
 };
-
-__device__ __forceinline__ Sel make_sel(uint32_t g, uint32_t kh, uint32_t kl) {
-    const uint32_t tail = (g < kl) ? 0xFFFFFFFFu : 0u;
-    Sel s;
-    s.f0 = (kh > 0u) ? 0xFFFFFFFFu : tail;  // kh == 0 -> tail
-    s.f1 = (kh > 1u) ? 0xFFFFFFFFu : ((kh == 1u) ? tail : 0u);
-    s.f2 = (kh > 2u) ? 0xFFFFFFFFu : ((kh == 2u) ? tail : 0u);
-    s.f3 = (kh > 3u) ? 0xFFFFFFFFu : ((kh == 3u) ? tail : 0u);
-    return s;
-}
-
-__device__ __forceinline__ uint32_t pick(uint32_t a, uint32_t b, const Sel &s) {
-    const uint32_t lo = (b & s.f1) | (~b & s.f0);  // a = 0
-    const uint32_t hi = (b & s.f3) | (~b & s.f2);  // a = 1
-    return (a & hi) | (~a & lo);
-}
 
 struct W2 {
     uint32_t lo, hi;
 };
 
-// The three draws of window k in substep s, reduced to the decision masks
-// D (diffusion), Am (annihilation, before conditioning on the tuple) and R
-// (fission direction, 1 = high).
+// Decision masks of one window: D (diffusion), Am (annihilation, before the
+// tuple condition) and R (fission direction, 1 = high), as 32-bit halves.
 struct Masks {
     W2 D, Am, R;
 };
 
+template <int KDH, int KPH>
 __device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
     const U4 d = philox10(U4{k, q8 | 0u, slo, shi}, ld.key0, ld.key1);
     const U4 a = philox10(U4{k, q8 | 1u, slo, shi}, ld.key0, ld.key1);
     const U4 r = philox10(U4{k, q8 | 2u, slo, shi}, ld.key0, ld.key1);
+    const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
+    const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
     Masks m;
-    const Sel sd = make_sel(r.z, ld.kd_hi, ld.kd_lo);
-    const Sel sa = make_sel(r.w, ld.kp_hi, ld.kp_lo);
-    // X1 = (x | y << 32), X2 = (z | w << 32): low halves x/z, high halves y/w
-    m.D.lo = pick(d.x, d.z, sd);
-    m.D.hi = pick(d.y, d.w, sd);
-    m.Am.lo = pick(a.x, a.z, sa);
-    m.Am.hi = pick(a.y, a.w, sa);
+    // X1 = x | y << 32, X2 = z | w << 32
+    m.D.lo = Decide<KDH>::half(d.x, d.z, td);
+    m.D.hi = Decide<KDH>::half(d.y, d.w, td);
+    m.Am.lo = Decide<KPH>::half(a.x, a.z, ta);
+    m.Am.hi = Decide<KPH>::half(a.y, a.w, ta);
     m.R.lo = r.x;
     m.R.hi = r.y;
     return m;
@@ -140,12 +145,135 @@ __device__ __forceinline__ void attempt(uint32_t (&w)[N + 2], uint32_t D, uint32
     w[0] |= F & ~R;      // low: site j-1
 }
 
+// S substeps of one tile held in LDS (see the file comment). `offs` holds the
+// phase's local sites, precomputed. The draws of the next substep are issued
+// after the current window's LDS reads so that their latency is covered.
+template <int N, int KDH, int KPH>
+__device__ __forceinline__ void run_substeps(uint64_t *lds, const uint32_t *offs, const LatDesc &ld,
+                                             uint32_t kg, uint32_t c, uint32_t ncols, uint64_t s0,
+                                             uint32_t S, uint32_t B, uint32_t ldw) {
+    const bool active = c < ncols;
+    Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
+    uint32_t o = __builtin_amdgcn_readfirstlane(offs[0]);
+    for (uint32_t it = 0; it < S; ++it) {
+        // window sites o-1 .. o+N of block c; they spill into block c-1 when
+        // o == 0 and into block c+1 when o+N >= B
+        const bool ok = active && (o > 0u || c > 0u) && (o + N < B || c + 1u < ncols);
+        int off[N + 2];
+#pragma unroll
+        for (int m = 0; m < N + 2; ++m) {
+            const int r = static_cast<int>(o) - 1 + m;
+            const int row = r < 0 ? r + static_cast<int>(B)
+                                  : (r >= static_cast<int>(B) ? r - static_cast<int>(B) : r);
+            const int sh = r < 0 ? -1 : (r >= static_cast<int>(B) ? 1 : 0);
+            off[m] = row * static_cast<int>(ldw) + sh;
+        }
+        uint32_t wl[N + 2], wh[N + 2];
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < N + 2; ++m) {
+                const uint64_t v = lds[off[m] + static_cast<int>(c)];
+                wl[m] = static_cast<uint32_t>(v);
+                wh[m] = static_cast<uint32_t>(v >> 32);
+            }
+        }
+        const uint32_t onext = (it + 1 < S) ? __builtin_amdgcn_readfirstlane(offs[it + 1]) : 0u;
+        const Masks nxt = window_masks<KDH, KPH>(ld, kg, s0 + it + 1);
+        if (ok) {
+            attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
+            attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
+#pragma unroll
+            for (int m = 0; m < N + 2; ++m)
+                lds[off[m] + static_cast<int>(c)] =
+                    static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
+        }
+        __syncthreads();
+        cur = nxt;
+        o = onext;
+    }
+}
+
+template <int N, int KDH>
+__device__ __forceinline__ void dispatch_kp(uint64_t *lds, const uint32_t *offs, const LatDesc &ld,
+                                            uint32_t kg, uint32_t c, uint32_t ncols, uint64_t s0,
+                                            uint32_t S, uint32_t B, uint32_t ldw) {
+    switch (ld.kp_hi) {
+        case 0: run_substeps<N, KDH, 0>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+        case 1: run_substeps<N, KDH, 1>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+        case 2: run_substeps<N, KDH, 2>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+        case 3: run_substeps<N, KDH, 3>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+        default: run_substeps<N, KDH, 4>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+    }
+}
+
+// Words moved per lane per batch between HBM and LDS: independent loads in
+// flight hide the memory latency.
+constexpr int kCopyBatch = 16;
+
+// Copy `total` words of a tile, ring blocks kfirst, kfirst+1, ... (mod nb),
+// from HBM (natural order) into LDS column-per-block. Lane i handles words
+// i, i+nthr, ...; (column, row, ring block) advance incrementally.
+__device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restrict__ ring,
+                                          uint32_t kfirst, uint32_t nb, uint32_t total, uint32_t B,
+                                          uint32_t ldw, uint32_t tid, uint32_t nthr) {
+    const uint32_t cstep = nthr / B, ostep = nthr - cstep * B, kstep = cstep % nb;
+    uint32_t c = tid / B, o = tid - c * B;
+    uint32_t kg = (kfirst + c) % nb;
+    for (uint32_t i0 = tid; i0 < total; i0 += kCopyBatch * nthr) {
+        uint64_t v[kCopyBatch];
+        uint32_t a[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            a[u] = o * ldw + c;
+            v[u] = (i0 + u * nthr < total) ? ring[static_cast<uint64_t>(kg) * B + o] : 0ull;
+            c += cstep;
+            o += ostep;
+            kg += kstep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+                ++kg;
+            }
+            if (kg >= nb) kg -= nb;
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * nthr < total) lds[a[u]] = v[u];
+    }
+}
+
+// Copy the interior columns hb .. hb+total/B-1 of the tile back to HBM, where
+// they are `total` consecutive words starting at `out`.
+__device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const uint64_t *lds,
+                                               uint32_t hb, uint32_t total, uint32_t B, uint32_t ldw,
+                                               uint32_t tid, uint32_t nthr) {
+    const uint32_t cstep = nthr / B, ostep = nthr - cstep * B;
+    uint32_t c = tid / B, o = tid - c * B;
+    for (uint32_t i0 = tid; i0 < total; i0 += kCopyBatch * nthr) {
+        uint64_t v[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            v[u] = (i0 + u * nthr < total) ? lds[o * ldw + hb + c] : 0ull;
+            c += cstep;
+            o += ostep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * nthr < total) out[i0 + u * nthr] = v[u];
+    }
+}
+
 template <int N>
 __global__ void __launch_bounds__(256)
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles, uint64_t s0,
           uint32_t S, uint32_t B, uint32_t hb, uint32_t ldw) {
-    extern __shared__ uint64_t lds[];  // [B][ldw]
+    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words, then S local sites
+    uint32_t *offs = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw);
     const TileDesc td = tiles[blockIdx.x];
     const LatDesc ld = lats[td.lat];
     const uint32_t nb = ld.nblocks;
@@ -157,79 +285,30 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         (static_cast<uint64_t>(td.k0) + static_cast<uint64_t>(nb) * ((hb + nb - 1u) / nb) - hb) %
         nb);
 
+    // ---- local sites of the phase, one lane per substep
+    for (uint32_t it = tid; it < S; it += nthr) offs[it] = substep_site(ld, s0 + it, B);
+
     // ---- load tile + halo: consecutive lanes read consecutive words
-    {
-        const uint64_t *ring = src + ld.base;
-        const uint32_t total = ncols * B;
-        const uint32_t cstep = nthr / B, ostep = nthr - cstep * B;
-        uint32_t c = tid / B, o = tid - c * B;
-        for (uint32_t i = tid; i < total; i += nthr) {
-            uint32_t kg = kfirst + c;
-            if (kg >= nb) kg %= nb;
-            lds[o * ldw + c] = ring[static_cast<uint64_t>(kg) * B + o];
-            c += cstep;
-            o += ostep;
-            if (o >= B) {
-                o -= B;
-                ++c;
-            }
-        }
-    }
+    load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     __syncthreads();
 
     // ---- S substeps in LDS, one window (block) per lane
-    const uint32_t c = tid;
-    const bool active = c < ncols;
-    uint32_t kg = kfirst + c;
-    if (kg >= nb) kg %= nb;
-    for (uint32_t it = 0; it < S; ++it) {
-        const uint64_t s = s0 + it;
-        const uint32_t o = substep_site(ld, s, B);
-        const Masks mk = window_masks(ld, kg, s);
-        // window sites o-1 .. o+N of block c; they spill into block c-1 when
-        // o == 0 and into block c+1 when o+N >= B
-        const bool ok = active && (o > 0u || c > 0u) && (o + N < B || c + 1u < ncols);
-        if (ok) {
-            int off[N + 2];
-#pragma unroll
-            for (int m = 0; m < N + 2; ++m) {
-                const int r = static_cast<int>(o) - 1 + m;
-                const int row = r < 0 ? r + static_cast<int>(B) : (r >= static_cast<int>(B) ? r - static_cast<int>(B) : r);
-                const int sh = r < 0 ? -1 : (r >= static_cast<int>(B) ? 1 : 0);
-                off[m] = row * static_cast<int>(ldw) + sh + static_cast<int>(c);
-            }
-            uint32_t wl[N + 2], wh[N + 2];
-#pragma unroll
-            for (int m = 0; m < N + 2; ++m) {
-                const uint64_t v = lds[off[m]];
-                wl[m] = static_cast<uint32_t>(v);
-                wh[m] = static_cast<uint32_t>(v >> 32);
-            }
-            attempt<N>(wl, mk.D.lo, mk.Am.lo, mk.R.lo);
-            attempt<N>(wh, mk.D.hi, mk.Am.hi, mk.R.hi);
-#pragma unroll
-            for (int m = 0; m < N + 2; ++m)
-                lds[off[m]] = static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
+    {
+        const uint32_t c = tid;
+        uint32_t kg = kfirst + c;
+        if (kg >= nb) kg %= nb;
+        switch (ld.kd_hi) {
+            case 0: dispatch_kp<N, 0>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+            case 1: dispatch_kp<N, 1>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+            case 2: dispatch_kp<N, 2>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+            case 3: dispatch_kp<N, 3>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+            default: dispatch_kp<N, 4>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
         }
-        __syncthreads();
     }
 
     // ---- write the interior back; it is contiguous in the ring
-    {
-        uint64_t *out = dst + ld.base + static_cast<uint64_t>(td.k0) * B;
-        const uint32_t total = td.kint * B;
-        const uint32_t cstep = nthr / B, ostep = nthr - cstep * B;
-        uint32_t cc = tid / B, o = tid - cc * B;
-        for (uint32_t i = tid; i < total; i += nthr) {
-            out[i] = lds[o * ldw + hb + cc];
-            cc += cstep;
-            o += ostep;
-            if (o >= B) {
-                o -= B;
-                ++cc;
-            }
-        }
-    }
+    store_interior(dst + ld.base + static_cast<uint64_t>(td.k0) * B, lds, hb, td.kint * B, B, ldw,
+                   tid, nthr);
 }
 
 __global__ void fill_words(uint64_t *__restrict__ dst, uint64_t n, uint64_t value) {
@@ -282,7 +361,7 @@ template <int N>
 hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                           const TileDesc *tiles, uint32_t ntiles, uint64_t s0, uint32_t S,
                           uint32_t B, const PhaseShape &sh, hipStream_t stream) {
-    const size_t lds = phase_lds_bytes(B, sh.ldw);
+    const size_t lds = phase_lds_bytes(B, sh.ldw, S);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N>),
@@ -298,8 +377,8 @@ hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lat
 
 }  // namespace
 
-size_t phase_lds_bytes(uint32_t B, uint32_t ldw) {
-    return static_cast<size_t>(B) * ldw * sizeof(uint64_t);
+size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S) {
+    return static_cast<size_t>(B) * ldw * sizeof(uint64_t) + static_cast<size_t>(S) * sizeof(uint32_t);
 }
 
 hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
