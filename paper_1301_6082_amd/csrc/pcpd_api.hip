@@ -95,7 +95,7 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
     const uint64_t hb = (reach + B - 1) / B;
     if (cols <= 2 * hb) return false;
     if (cols > 256) return false;
-    uint32_t ldw = cols | 1u;
+    const uint32_t ldw = (cols + 3u) | 1u;  // three spare columns, odd pitch
     if (pcpd::phase_lds_bytes(B, ldw, phase_max) > pcpd::kMaxLdsBytes) return false;
     out->cols = cols;
     out->threads = (cols + 63u) / 64u * 64u;

@@ -15,7 +15,8 @@
 //
 // LDS layout: offset-major, word (block c, local site o) at o*ldw + c. All
 // lanes of a substep touch the same row o, consecutive columns: no bank
-// conflicts. ldw is odd so the row-major HBM<->LDS copies spread over banks.
+// conflicts. ldw is odd so the row-major HBM<->LDS copies spread over banks,
+// and leaves three spare columns past the tile.
 
 #include <hip/hip_runtime.h>
 
@@ -106,13 +107,36 @@ struct Masks {
     W2 D, Am, R;
 };
 
+// The three draws of one window advanced round by round together: six
+// independent 32x32->64 products per round keep the VALU pipeline full even
+// with one wavefront per SIMD. Round 1 is identical for the three draws
+// (they differ only in counter word 1) and is computed once by the compiler.
+__device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
+            const uint64_t pb = static_cast<uint64_t>(c[j].z) * kMulB;
+            U4 nx;
+            nx.x = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c[j].y, ka, 0x96);
+            nx.y = static_cast<uint32_t>(pb);
+            nx.z = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c[j].w, kb, 0x96);
+            nx.w = static_cast<uint32_t>(pa);
+            c[j] = nx;
+        }
+        ka += kWeylA;
+        kb += kWeylB;
+    }
+}
+
 template <int KDH, int KPH>
 __device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
-    const U4 d = philox10(U4{k, q8 | 0u, slo, shi}, ld.key0, ld.key1);
-    const U4 a = philox10(U4{k, q8 | 1u, slo, shi}, ld.key0, ld.key1);
-    const U4 r = philox10(U4{k, q8 | 2u, slo, shi}, ld.key0, ld.key1);
+    U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
+    philox10_x3(x, ld.key0, ld.key1);
+    const U4 &d = x[0], &a = x[1], &r = x[2];
     const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
     const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
     Masks m;
@@ -145,64 +169,80 @@ __device__ __forceinline__ void attempt(uint32_t (&w)[N + 2], uint32_t D, uint32
     w[0] |= F & ~R;      // low: site j-1
 }
 
-// S substeps of one tile held in LDS (see the file comment). `offs` holds the
-// phase's local sites, precomputed. The draws of the next substep are issued
-// after the current window's LDS reads so that their latency is covered.
-template <int N, int KDH, int KPH>
-__device__ __forceinline__ void run_substeps(uint64_t *lds, const uint32_t *offs, const LatDesc &ld,
-                                             uint32_t kg, uint32_t c, uint32_t ncols, uint64_t s0,
-                                             uint32_t S, uint32_t B, uint32_t ldw) {
-    const bool active = c < ncols;
-    Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
-    uint32_t o = __builtin_amdgcn_readfirstlane(offs[0]);
-    for (uint32_t it = 0; it < S; ++it) {
-        // window sites o-1 .. o+N of block c; they spill into block c-1 when
-        // o == 0 and into block c+1 when o+N >= B
-        const bool ok = active && (o > 0u || c > 0u) && (o + N < B || c + 1u < ncols);
-        int off[N + 2];
+// LDS word offsets (in words) of the window of substep site o, relative to
+// the lane's column: site o-1+m sits in row (o-1+m) mod B of column c-1, c or
+// c+1. Integer arithmetic only, so that it stays on the scalar unit.
+template <int N>
+__device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t ldw,
+                                               int (&base)[N + 2]) {
+    const int W = static_cast<int>(B * ldw) - 1;  // one row-block back plus one column
 #pragma unroll
-        for (int m = 0; m < N + 2; ++m) {
-            const int r = static_cast<int>(o) - 1 + m;
-            const int row = r < 0 ? r + static_cast<int>(B)
-                                  : (r >= static_cast<int>(B) ? r - static_cast<int>(B) : r);
-            const int sh = r < 0 ? -1 : (r >= static_cast<int>(B) ? 1 : 0);
-            off[m] = row * static_cast<int>(ldw) + sh;
-        }
-        uint32_t wl[N + 2], wh[N + 2];
-        if (ok) {
+    for (int m = 0; m < N + 2; ++m) {
+        const int r = static_cast<int>(o) - 1 + m;
+        const int below = static_cast<int>(static_cast<uint32_t>(r) >> 31);            // r < 0
+        const int above = 1 - static_cast<int>(static_cast<uint32_t>(r - static_cast<int>(B)) >> 31);  // r >= B
+        base[m] = r * static_cast<int>(ldw) + (below - above) * W;
+    }
+}
+
+// S substeps of one tile held in LDS (see the file comment). Each wavefront
+// draws the local sites of 64 substeps at a time, one per lane, and reads
+// them back with v_readlane, so no memory wait precedes the next substep.
+// The draws of the next substep are issued after the current window's LDS
+// reads so that their latency is covered. Lanes whose window would leave the
+// loaded columns (block 0 when o == 0, the last block when o+N >= B, lanes
+// past the tile) work on the spare columns trash-1 .. trash+1 instead, so the
+// loop has no divergence.
+template <int N, int KDH, int KPH>
+__device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+                                             uint32_t c, uint32_t ncols, uint32_t trash,
+                                             uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
+    const uint32_t lane = __lane_id();
+    const bool active = c < ncols;
+    const bool first = c == 0u, last = c + 1u == ncols;
+    Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
+    for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+        const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
+        const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint32_t o = __builtin_amdgcn_readlane(sites, j);
+            const uint64_t s = s0 + it0 + j;
+            // window sites o-1 .. o+N of block c; they spill into block c-1
+            // when o == 0 and into block c+1 when o+N >= B
+            const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
+            const int col = static_cast<int>(ok ? c : trash);
+            int base[N + 2];
+            window_offsets<N>(o, B, ldw, base);
+            uint32_t wl[N + 2], wh[N + 2];
 #pragma unroll
             for (int m = 0; m < N + 2; ++m) {
-                const uint64_t v = lds[off[m] + static_cast<int>(c)];
+                const uint64_t v = lds[base[m] + col];
                 wl[m] = static_cast<uint32_t>(v);
                 wh[m] = static_cast<uint32_t>(v >> 32);
             }
-        }
-        const uint32_t onext = (it + 1 < S) ? __builtin_amdgcn_readfirstlane(offs[it + 1]) : 0u;
-        const Masks nxt = window_masks<KDH, KPH>(ld, kg, s0 + it + 1);
-        if (ok) {
+            const Masks nxt = window_masks<KDH, KPH>(ld, kg, s + 1);
             attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
             attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
 #pragma unroll
             for (int m = 0; m < N + 2; ++m)
-                lds[off[m] + static_cast<int>(c)] =
+                lds[base[m] + col] =
                     static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
+            __syncthreads();
+            cur = nxt;
         }
-        __syncthreads();
-        cur = nxt;
-        o = onext;
     }
 }
 
 template <int N, int KDH>
-__device__ __forceinline__ void dispatch_kp(uint64_t *lds, const uint32_t *offs, const LatDesc &ld,
-                                            uint32_t kg, uint32_t c, uint32_t ncols, uint64_t s0,
-                                            uint32_t S, uint32_t B, uint32_t ldw) {
+__device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
+                                            uint32_t kg, uint32_t c, uint32_t ncols, uint32_t trash,
+                                            uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
     switch (ld.kp_hi) {
-        case 0: run_substeps<N, KDH, 0>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-        case 1: run_substeps<N, KDH, 1>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-        case 2: run_substeps<N, KDH, 2>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-        case 3: run_substeps<N, KDH, 3>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-        default: run_substeps<N, KDH, 4>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+        case 0: run_substeps<N, KDH, 0>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+        case 1: run_substeps<N, KDH, 1>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+        case 2: run_substeps<N, KDH, 2>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+        case 3: run_substeps<N, KDH, 3>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+        default: run_substeps<N, KDH, 4>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
     }
 }
 
@@ -267,13 +307,14 @@ __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const
     }
 }
 
+// One workgroup per tile; LDS allows one such workgroup per CU, so the
+// compiler may spend registers on instruction-level parallelism.
 template <int N>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles, uint64_t s0,
-          uint32_t S, uint32_t B, uint32_t hb, uint32_t ldw) {
-    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words, then S local sites
-    uint32_t *offs = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw);
+          uint32_t S, uint32_t B, uint32_t hb, uint32_t cols, uint32_t ldw) {
+    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
     const TileDesc td = tiles[blockIdx.x];
     const LatDesc ld = lats[td.lat];
     const uint32_t nb = ld.nblocks;
@@ -285,9 +326,6 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         (static_cast<uint64_t>(td.k0) + static_cast<uint64_t>(nb) * ((hb + nb - 1u) / nb) - hb) %
         nb);
 
-    // ---- local sites of the phase, one lane per substep
-    for (uint32_t it = tid; it < S; it += nthr) offs[it] = substep_site(ld, s0 + it, B);
-
     // ---- load tile + halo: consecutive lanes read consecutive words
     load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     __syncthreads();
@@ -295,14 +333,15 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     // ---- S substeps in LDS, one window (block) per lane
     {
         const uint32_t c = tid;
+        const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
         uint32_t kg = kfirst + c;
         if (kg >= nb) kg %= nb;
         switch (ld.kd_hi) {
-            case 0: dispatch_kp<N, 0>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-            case 1: dispatch_kp<N, 1>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-            case 2: dispatch_kp<N, 2>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-            case 3: dispatch_kp<N, 3>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
-            default: dispatch_kp<N, 4>(lds, offs, ld, kg, c, ncols, s0, S, B, ldw); break;
+            case 0: dispatch_kp<N, 0>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+            case 1: dispatch_kp<N, 1>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+            case 2: dispatch_kp<N, 2>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+            case 3: dispatch_kp<N, 3>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+            default: dispatch_kp<N, 4>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
         }
     }
 
@@ -371,14 +410,15 @@ hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lat
         attr_set = true;
     }
     hipLaunchKernelGGL(brs_phase<N>, dim3(ntiles), dim3(sh.threads), lds, stream, src, dst, lats,
-                       tiles, s0, S, B, sh.hb, sh.ldw);
+                       tiles, s0, S, B, sh.hb, sh.cols, sh.ldw);
     return hipGetLastError();
 }
 
 }  // namespace
 
 size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S) {
-    return static_cast<size_t>(B) * ldw * sizeof(uint64_t) + static_cast<size_t>(S) * sizeof(uint32_t);
+    (void)S;
+    return static_cast<size_t>(B) * ldw * sizeof(uint64_t);
 }
 
 hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
