@@ -98,7 +98,7 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
     const uint32_t ldw = (cols + 3u) | 1u;  // three spare columns, odd pitch
     if (pcpd::phase_lds_bytes(B, ldw, phase_max) > pcpd::kMaxLdsBytes) return false;
     out->cols = cols;
-    out->threads = (cols + 63u) / 64u * 64u;
+    out->threads = 2u * ((cols + 63u) / 64u * 64u);  // two teams of one lane per block
     out->ldw = ldw;
     out->hb = static_cast<uint32_t>(hb);
     return true;

@@ -52,7 +52,7 @@ constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 // Kernel shape of one phase launch.
 struct PhaseShape {
     uint32_t cols;     // blocks held in LDS per workgroup (interior + 2*halo)
-    uint32_t threads;  // workgroup size (multiple of 64, >= cols)
+    uint32_t threads;  // workgroup size: two teams of a multiple of 64 >= cols lanes
     uint32_t ldw;      // LDS row pitch in words (>= cols + 3, odd)
     uint32_t hb;       // halo blocks on each side
 };

@@ -185,64 +185,72 @@ __device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t 
     }
 }
 
-// S substeps of one tile held in LDS (see the file comment). Each wavefront
-// draws the local sites of 64 substeps at a time, one per lane, and reads
-// them back with v_readlane, so no memory wait precedes the next substep.
-// The draws of the next substep are issued after the current window's LDS
-// reads so that their latency is covered. Lanes whose window would leave the
-// loaded columns (block 0 when o == 0, the last block when o+N >= B, lanes
-// past the tile) work on the spare columns trash-1 .. trash+1 instead, so the
-// loop has no divergence.
+// S substeps of one tile held in LDS (see the file comment), by two teams
+// of lanes, each with one lane per block. Team t applies the substeps
+// it = t, t+2, t+4, ...: in every interval between two barriers one team
+// updates the windows in LDS with masks it drew earlier while the other team
+// draws the masks of its own next substep. Each SIMD thus runs one wavefront
+// of either kind, and the short, latency-bound update path overlaps the
+// arithmetic of the draws. Each wavefront draws the local sites of 64
+// substeps at a time, one per lane, and reads them back with v_readlane.
+// Lanes whose window would leave the loaded columns (block 0 when o == 0,
+// the last block when o+N >= B, lanes past the tile) work on the spare
+// columns trash-1 .. trash+1 instead, so no branch depends on the lane.
 template <int N, int KDH, int KPH>
 __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, uint32_t kg,
-                                             uint32_t c, uint32_t ncols, uint32_t trash,
-                                             uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
+                                             uint32_t c, uint32_t team, uint32_t ncols,
+                                             uint32_t trash, uint64_t s0, uint32_t S, uint32_t B,
+                                             uint32_t ldw) {
     const uint32_t lane = __lane_id();
     const bool active = c < ncols;
     const bool first = c == 0u, last = c + 1u == ncols;
-    Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
+    Masks cur{};
+    if (team == 0u) cur = window_masks<KDH, KPH>(ld, kg, s0);
     for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
         const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
         const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
         for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t o = __builtin_amdgcn_readlane(sites, j);
-            const uint64_t s = s0 + it0 + j;
-            // window sites o-1 .. o+N of block c; they spill into block c-1
-            // when o == 0 and into block c+1 when o+N >= B
-            const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
-            const int col = static_cast<int>(ok ? c : trash);
-            int base[N + 2];
-            window_offsets<N>(o, B, ldw, base);
-            uint32_t wl[N + 2], wh[N + 2];
+            const uint32_t it = it0 + j;
+            if ((it & 1u) == team) {
+                const uint32_t o = __builtin_amdgcn_readlane(sites, j);
+                // window sites o-1 .. o+N of block c; they spill into block
+                // c-1 when o == 0 and into block c+1 when o+N >= B
+                const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
+                const int col = static_cast<int>(ok ? c : trash);
+                int base[N + 2];
+                window_offsets<N>(o, B, ldw, base);
+                uint32_t wl[N + 2], wh[N + 2];
 #pragma unroll
-            for (int m = 0; m < N + 2; ++m) {
-                const uint64_t v = lds[base[m] + col];
-                wl[m] = static_cast<uint32_t>(v);
-                wh[m] = static_cast<uint32_t>(v >> 32);
+                for (int m = 0; m < N + 2; ++m) {
+                    const uint64_t v = lds[base[m] + col];
+                    wl[m] = static_cast<uint32_t>(v);
+                    wh[m] = static_cast<uint32_t>(v >> 32);
+                }
+                attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
+                attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
+#pragma unroll
+                for (int m = 0; m < N + 2; ++m)
+                    lds[base[m] + col] =
+                        static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
+            } else if (it + 1u < S) {
+                cur = window_masks<KDH, KPH>(ld, kg, s0 + it + 1u);
             }
-            const Masks nxt = window_masks<KDH, KPH>(ld, kg, s + 1);
-            attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
-            attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
-#pragma unroll
-            for (int m = 0; m < N + 2; ++m)
-                lds[base[m] + col] =
-                    static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
             __syncthreads();
-            cur = nxt;
         }
     }
 }
 
 template <int N, int KDH>
 __device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
-                                            uint32_t kg, uint32_t c, uint32_t ncols, uint32_t trash,
+                                            uint32_t kg, uint32_t c, uint32_t team, uint32_t ncols,
+                                            uint32_t trash,
                                             uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
     switch (ld.kp_hi) {
-        case 0: run_substeps<N, KDH, 0>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-        case 1: run_substeps<N, KDH, 1>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-        case 2: run_substeps<N, KDH, 2>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-        case 3: run_substeps<N, KDH, 3>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-        default: run_substeps<N, KDH, 4>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+        case 0: run_substeps<N, KDH, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 1: run_substeps<N, KDH, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 2: run_substeps<N, KDH, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 3: run_substeps<N, KDH, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        default: run_substeps<N, KDH, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
     }
 }
 
@@ -307,10 +315,10 @@ __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const
     }
 }
 
-// One workgroup per tile; LDS allows one such workgroup per CU, so the
-// compiler may spend registers on instruction-level parallelism.
+// One workgroup per tile, two lanes per block (the two teams); LDS allows
+// one such workgroup per CU, two wavefronts per SIMD.
 template <int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles, uint64_t s0,
           uint32_t S, uint32_t B, uint32_t hb, uint32_t cols, uint32_t ldw) {
@@ -332,16 +340,18 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
 
     // ---- S substeps in LDS, one window (block) per lane
     {
-        const uint32_t c = tid;
+        const uint32_t half = nthr >> 1;
+        const uint32_t team = tid >= half ? 1u : 0u;
+        const uint32_t c = tid - team * half;
         const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
         uint32_t kg = kfirst + c;
         if (kg >= nb) kg %= nb;
         switch (ld.kd_hi) {
-            case 0: dispatch_kp<N, 0>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-            case 1: dispatch_kp<N, 1>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-            case 2: dispatch_kp<N, 2>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-            case 3: dispatch_kp<N, 3>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
-            default: dispatch_kp<N, 4>(lds, ld, kg, c, ncols, trash, s0, S, B, ldw); break;
+            case 0: dispatch_kp<N, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 1: dispatch_kp<N, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 2: dispatch_kp<N, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 3: dispatch_kp<N, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            default: dispatch_kp<N, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
         }
     }
 
