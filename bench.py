@@ -25,22 +25,48 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer-VALU op model of one word-update (64 site updates): issue slots of
-# the algorithm's arithmetic, counted on gfx950 with 32x32->64 multiplies at a
-# quarter of the full rate (see the design notes for the derivation).
-OPS_PER_WORD_UPDATE = 352
-PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x lanes x clock: 3.93e13 slots/s
+# Integer-VALU op model of one PCPD word-update (64 site updates): the VALU
+# instructions of the method's arithmetic as issued on gfx950, each one issue
+# slot per lane (32x32->64 products run at full rate on gfx950): three
+# Philox-4x32-10 draws = 53 products + 56 three-input XORs, two probability
+# decisions = 8, the bit-sliced PCPD attempt = 22. Addressing, register moves,
+# halo windows and tile copies are not counted.
+OPS_PER_WORD_UPDATE = 139
+PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x 64 lanes x 2.4 GHz = 3.93e13 ops/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "brs_phase_pcpd_L2p20_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "sweep.hip")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mc-per-step", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-units", type=int, default=8)
+    ap.add_argument("--cpu-sample-units", type=int, default=0,
+                    help="(instance, plane) units for the oracle timing; 0 = one per host thread")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="copy 1 GiB device-to-device three times first (counter calibration)")
     return ap.parse_args()
+
+
+def kernel_traffic(tile):
+    """HBM bytes per phase launch from the committed counter profile, if it
+    was taken on the current kernel source and tile shape; else None."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel_sha256:", "tile:")))
+    digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("kernel_sha256", "").strip() != digest:
+        return None
+    if fields.get("tile", "").strip() != f"{tile[0]}x{tile[1]}":
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(wl, n_units: int):
@@ -49,6 +75,8 @@ def cpu_baseline(wl, n_units: int):
     from oracle import oracle
 
     oracle.build(force=False)
+    if n_units <= 0:
+        n_units = max(1, oracle.max_threads())
     units = []
     steps = 2
     for u in range(n_units):
@@ -90,8 +118,16 @@ def main():
     rec_times = [t for t in wl.times]
     su_per_mc = sum(64 * wl.planes * inst.L for inst in wl.instances)
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
-    stream = torch.cuda.current_stream()
 
     def step_times(k):
         lo, hi = k * M, (k + 1) * M
@@ -102,29 +138,28 @@ def main():
         sim.run(step_times(k))
     torch.cuda.synchronize()
 
+    # the dominant kernel (the sweep's phase kernel) is timed by HIP events
+    # that the library records around each launch on its own stream
+    sim.profile(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     counts = None
     for k in range(args.warmup, args.warmup + args.steps):
         counts = sim.run(step_times(k))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    kernel_ms, launches = sim.profile_read()
+    sim.profile(False)
     assert sim.time == total_steps
     site_updates = su_per_mc * M * args.steps
     value = site_updates / elapsed
 
-    # dominant kernel: the phase kernel, timed with events on its stream
     tuning = sim.get_tuning()
-    phases_per_mc = -(-wl.B // tuning[1])
-    n_probe = 200
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    sim.sweep(n_probe)
-    ev1.record(stream)
-    ev1.synchronize()
-    launch_ms = ev0.elapsed_time(ev1) / (n_probe * phases_per_mc)
-    word_updates_per_launch = su_per_mc / 64 / phases_per_mc
-    ops_per_launch = OPS_PER_WORD_UPDATE * word_updates_per_launch
+    launch_ms = kernel_ms / launches
+    word_updates = site_updates / 64          # interior windows, all launches
+    ops_per_launch = OPS_PER_WORD_UPDATE * word_updates / launches
     achieved = ops_per_launch / (launch_ms * 1e-3)
+    traffic = kernel_traffic(tuning)
     rho = counts[-1, :, :, 0].astype(np.float64).sum(axis=1) / (64 * wl.planes * (1 << 20))
 
     cpu = None
@@ -151,10 +186,12 @@ def main():
                    "records": "64 log-spaced times of a 1e5-step run, plus each step end",
                    "tile_cols": tuning[0], "phase_max": tuning[1]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s (int32 VALU issue slots)",
-                     "frac": achieved / PEAK_SLOTS, "traffic": None,
-                     "kernel": "brs_phase<2>", "launch_ms": launch_ms,
-                     "ops_per_word_update": OPS_PER_WORD_UPDATE},
+                     "unit": "Tops/s (int32 VALU lane-ops)",
+                     "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+                     "kernel": "brs_phase<2>", "launch_ms": launch_ms, "launches": launches,
+                     "ops_per_word_update": OPS_PER_WORD_UPDATE,
+                     "site_updates_per_s_at_peak": PEAK_SLOTS / OPS_PER_WORD_UPDATE * 64,
+                     "kernel_share_of_wall": kernel_ms * 1e-3 / elapsed},
         "cpu_baseline": cpu,
         "rho_at_end": [round(float(x), 5) for x in rho],
     }

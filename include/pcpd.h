@@ -152,6 +152,14 @@ PCPD_API int pcpd_sync(pcpd_ctx *ctx);
 PCPD_API int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning);
 PCPD_API int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning);
 
+/* Timing of the sweep's phase kernels: while enabled, every phase launch is
+ * bracketed by a pair of HIP events on the context's stream.
+ * pcpd_profile_read synchronises, returns the summed kernel time in
+ * milliseconds and the number of launches since the last read, and resets
+ * both. Enabling does not change results. */
+PCPD_API int pcpd_profile(pcpd_ctx *ctx, int enable);
+PCPD_API int pcpd_profile_read(pcpd_ctx *ctx, double *kernel_ms, uint64_t *launches);
+
 /* Release the context and everything the library allocated for it. */
 PCPD_API int pcpd_free(pcpd_ctx *ctx);
 

@@ -54,6 +54,10 @@ struct pcpd_ctx {
 
     uint64_t t = 0;
     bool broken = false;
+
+    bool profiling = false;
+    std::vector<hipEvent_t> events;  // pairs (start, stop) per profiled launch
+    size_t events_used = 0;
 };
 
 namespace {
@@ -104,15 +108,20 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
     return true;
 }
 
-// Default shape: the widest tile that fits LDS, one window per lane, and a
-// phase of one Monte Carlo step when B is small enough.
+// Default shape: phases of two Monte Carlo steps (at most 128 substeps) and
+// the widest tile of at most 128 blocks that lets two workgroups share a CU
+// (half the LDS each), so that one workgroup's barriers and tile copies
+// overlap the other's arithmetic; failing that, any tile that fits.
 bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_max) {
-    uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(B, 64));
+    uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(2 * B, 128));
     for (; pm >= 1; pm = pm / 2) {
-        for (uint32_t cols = 256; cols >= 1; --cols) {
-            if (make_shape(n, B, cols, pm, shape)) {
-                *phase_max = pm;
-                return true;
+        for (uint32_t lds_cap : {pcpd::kMaxLdsBytes / 2, pcpd::kMaxLdsBytes}) {
+            for (uint32_t cols = 128; cols >= 1; --cols) {
+                if (make_shape(n, B, cols, pm, shape) &&
+                    pcpd::phase_lds_bytes(B, shape->ldw, pm) <= lds_cap) {
+                    *phase_max = pm;
+                    return true;
+                }
             }
         }
         if (pm == 1) break;
@@ -173,15 +182,35 @@ hipError_t ensure_count_slots(pcpd_ctx *ctx, uint32_t slots) {
     return hipSuccess;
 }
 
+// A (start, stop) event pair from the context's pool.
+hipError_t next_event_pair(pcpd_ctx *ctx, hipEvent_t **pair) {
+    while (ctx->events.size() < ctx->events_used + 2) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        ctx->events.push_back(e);
+    }
+    *pair = &ctx->events[ctx->events_used];
+    ctx->events_used += 2;
+    return hipSuccess;
+}
+
 // Enqueue n_steps Monte Carlo steps as phases of at most phase_max substeps.
 hipError_t enqueue_sweep(pcpd_ctx *ctx, uint64_t n_steps) {
     uint64_t sub = ctx->t * ctx->B;
     const uint64_t end = (ctx->t + n_steps) * ctx->B;
     while (sub < end) {
         const uint32_t S = static_cast<uint32_t>(std::min<uint64_t>(ctx->phase_max, end - sub));
+        hipEvent_t *ev = nullptr;
+        if (ctx->profiling) {
+            hipError_t e = next_event_pair(ctx, &ev);
+            if (e == hipSuccess) e = hipEventRecord(ev[0], ctx->stream);
+            if (e != hipSuccess) return e;
+        }
         hipError_t e = pcpd::launch_phase(ctx->n, ctx->buf[ctx->cur], ctx->buf[ctx->cur ^ 1],
                                           ctx->d_lats, ctx->d_tiles, ctx->ntiles, sub, S, ctx->B,
                                           ctx->shape, ctx->stream);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
         if (e != hipSuccess) return e;
         ctx->cur ^= 1;
         sub += S;
@@ -205,6 +234,7 @@ void release(pcpd_ctx *ctx) {
     if (ctx->d_chunks) (void)hipFree(ctx->d_chunks);
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -444,6 +474,31 @@ int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
     if (!ctx || !tuning) return PCPD_EINVAL;
     tuning->tile_cols = ctx->shape.cols;
     tuning->phase_max = ctx->phase_max;
+    return PCPD_OK;
+}
+
+int pcpd_profile(pcpd_ctx *ctx, int enable) {
+    if (!ctx) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    ctx->profiling = enable != 0;
+    return PCPD_OK;
+}
+
+int pcpd_profile_read(pcpd_ctx *ctx, double *kernel_ms, uint64_t *launches) {
+    if (!ctx || !kernel_ms || !launches) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < ctx->events_used; i += 2) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
+        if (e != hipSuccess) return fail(ctx, e);
+        total += ms;
+    }
+    *kernel_ms = total;
+    *launches = ctx->events_used / 2;
+    ctx->events_used = 0;
     return PCPD_OK;
 }
 

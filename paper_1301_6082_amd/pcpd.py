@@ -49,7 +49,8 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcpd_run",
            "pcpd_get_lattice", "pcpd_set_lattice", "pcpd_time", "pcpd_sync",
-           "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_free", "pcpd_strerror"]
+           "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_profile", "pcpd_profile_read",
+           "pcpd_free", "pcpd_strerror"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -70,6 +71,8 @@ def load_library(path: str = LIB_PATH):
         "pcpd_sync": ([vp], ctypes.c_int),
         "pcpd_set_tuning": ([vp, P(Tuning)], ctypes.c_int),
         "pcpd_get_tuning": ([vp, P(Tuning)], ctypes.c_int),
+        "pcpd_profile": ([vp, ctypes.c_int], ctypes.c_int),
+        "pcpd_profile_read": ([vp, P(ctypes.c_double), P(u64)], ctypes.c_int),
         "pcpd_free": ([vp], ctypes.c_int),
         "pcpd_strerror": ([ctypes.c_int], ctypes.c_char_p),
     }
@@ -203,6 +206,17 @@ class Sim:
         tu = Tuning()
         _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
         return int(tu.tile_cols), int(tu.phase_max)
+
+    def profile(self, enable: bool = True):
+        """Bracket every phase-kernel launch with HIP events on the stream."""
+        _check(_lib.pcpd_profile(self._ctx, 1 if enable else 0), "pcpd_profile")
+
+    def profile_read(self):
+        """(summed phase-kernel milliseconds, launches) since the last read."""
+        ms, n = ctypes.c_double(), u64()
+        _check(_lib.pcpd_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n)),
+               "pcpd_profile_read")
+        return float(ms.value), int(n.value)
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

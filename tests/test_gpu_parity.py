@@ -209,3 +209,19 @@ def test_cfg3_batch_sampled(pcpd):
             n, pair = per_sample_counts(lat[i])
             for b in (3, 60):
                 assert n[b] == r.n[-1, b] and pair[b] == r.pair[-1, b]
+
+
+def test_profiling_does_not_change_results(pcpd):
+    insts = [Instance(0.12, 0.4, 64 * 301, 3)]
+    out = []
+    for prof in (False, True):
+        with pcpd.Sim(2, 64, 1, 11, insts) as sim:
+            sim.profile(prof)
+            sim.sweep(6)
+            ms, n = sim.profile_read()
+            out.append(sim.get_lattice(0))
+            if prof:
+                assert n == -(-6 * 64 // sim.get_tuning()[1]) and ms > 0
+            else:
+                assert n == 0
+    np.testing.assert_array_equal(out[0], out[1])
