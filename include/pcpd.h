@@ -152,6 +152,25 @@ PCPD_API int pcpd_sync(pcpd_ctx *ctx);
 PCPD_API int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning);
 PCPD_API int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning);
 
+/* Options of a context (bit flags). */
+typedef enum {
+    PCPD_OPT_GRAPH = 1  /* capture each pcpd_sweep / pcpd_run batch into a HIP graph on first
+                           use and replay it when the same batch (same Monte Carlo step
+                           increments and record slots, same copy parity) comes again; the
+                           kernels read the substep index from a device clock, so a replay is
+                           valid at any starting time. Ignored while profiling. */
+} pcpd_option;
+
+PCPD_API int pcpd_set_options(pcpd_ctx *ctx, uint32_t options);
+
+/* Pick the kernel shape by timing candidate tiles (blocks per tile x substeps
+ * per phase) on this context's own lattice: each trial reads the current copy
+ * and writes the spare one, so the state is unchanged. `reps` timed launches
+ * per candidate (0 = 3). The choice is cached per process for contexts of the
+ * same model, block width and ring sizes, applied to the context and returned
+ * in *chosen (may be NULL). Results never depend on the shape. */
+PCPD_API int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen);
+
 /* Timing of the sweep's phase kernels: while enabled, every phase launch is
  * bracketed by a pair of HIP events on the context's stream.
  * pcpd_profile_read synchronises, returns the summed kernel time in

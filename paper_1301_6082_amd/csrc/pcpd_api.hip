@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -58,11 +59,34 @@ struct pcpd_ctx {
     bool profiling = false;
     std::vector<hipEvent_t> events;  // pairs (start, stop) per profiled launch
     size_t events_used = 0;
+
+    uint64_t *d_clock = nullptr;     // substep index at the start of the next enqueued batch
+    uint32_t options = 0;            // PCPD_OPT_* flags
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    struct GraphEntry;
+    std::vector<GraphEntry *> graphs;  // cached executable graphs, oldest first
+};
+
+// One step of a batch: sweep `steps` Monte Carlo steps, then record the
+// counts into slot `slot` (if >= 0).
+struct BatchOp {
+    uint64_t steps;
+    int32_t slot;
+    bool operator==(const BatchOp &o) const { return steps == o.steps && slot == o.slot; }
+};
+
+// A captured batch. It is valid for any starting time (the kernels read the
+// device clock) but only for the same buffers, parity, tiles and slots.
+struct pcpd_ctx::GraphEntry {
+    std::vector<BatchOp> ops;
+    int cur_in = 0, cur_out = 0;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
 constexpr uint32_t kDenChunkWords = 8192;
+constexpr size_t kMaxGraphs = 16;
 
 // K = rint(q * 2^34): the integer threshold of a probability-q decision.
 // ldexp is exact and rint rounds half to even.
@@ -136,7 +160,10 @@ int fail(pcpd_ctx *ctx, hipError_t e) {
                                                                        : PCPD_EDEVICE;
 }
 
+void drop_graphs(pcpd_ctx *ctx);
+
 hipError_t build_tiles(pcpd_ctx *ctx) {
+    drop_graphs(ctx);  // captured launches refer to the old tile table
     std::vector<TileDesc> tiles;
     const uint32_t kmax = ctx->shape.cols - 2 * ctx->shape.hb;
     for (uint32_t l = 0; l < ctx->nlat; ++l) {
@@ -164,6 +191,7 @@ hipError_t build_tiles(pcpd_ctx *ctx) {
 
 hipError_t ensure_count_slots(pcpd_ctx *ctx, uint32_t slots) {
     if (slots <= ctx->count_slots) return hipSuccess;
+    drop_graphs(ctx);  // captured density launches refer to the old slots
     if (ctx->d_counts) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return e;
@@ -195,34 +223,121 @@ hipError_t next_event_pair(pcpd_ctx *ctx, hipEvent_t **pair) {
     return hipSuccess;
 }
 
-// Enqueue n_steps Monte Carlo steps as phases of at most phase_max substeps.
-hipError_t enqueue_sweep(pcpd_ctx *ctx, uint64_t n_steps) {
-    uint64_t sub = ctx->t * ctx->B;
-    const uint64_t end = (ctx->t + n_steps) * ctx->B;
-    while (sub < end) {
-        const uint32_t S = static_cast<uint32_t>(std::min<uint64_t>(ctx->phase_max, end - sub));
-        hipEvent_t *ev = nullptr;
-        if (ctx->profiling) {
-            hipError_t e = next_event_pair(ctx, &ev);
-            if (e == hipSuccess) e = hipEventRecord(ev[0], ctx->stream);
+void drop_graphs(pcpd_ctx *ctx) {
+    for (auto *g : ctx->graphs) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        delete g;
+    }
+    ctx->graphs.clear();
+}
+
+// Enqueue a batch on `stream`: phases of at most phase_max substeps reading
+// the device clock plus their offset in the batch, density records into their
+// slots, and one clock advance at the end. Returns the index of the copy that
+// holds the lattice afterwards.
+hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream_t stream,
+                       bool profile, int *cur_out) {
+    int cur = ctx->cur;
+    uint64_t rel = 0;
+    for (const BatchOp &op : ops) {
+        const uint64_t end = rel + op.steps * ctx->B;
+        while (rel < end) {
+            const uint32_t S = static_cast<uint32_t>(std::min<uint64_t>(ctx->phase_max, end - rel));
+            hipEvent_t *ev = nullptr;
+            if (profile) {
+                hipError_t e = next_event_pair(ctx, &ev);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = pcpd::launch_phase(ctx->n, ctx->buf[cur], ctx->buf[cur ^ 1], ctx->d_lats,
+                                              ctx->d_tiles, ctx->ntiles, ctx->d_clock, rel, S,
+                                              ctx->B, ctx->shape, stream);
+            if (e == hipSuccess && ev) e = hipEventRecord(ev[1], stream);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+            rel += S;
+        }
+        if (op.slot >= 0) {
+            hipError_t e = pcpd::launch_density(
+                ctx->buf[cur], ctx->d_lats, ctx->d_chunks, ctx->nchunks,
+                ctx->d_counts + static_cast<size_t>(op.slot) * ctx->nlat, ctx->nlat, stream);
             if (e != hipSuccess) return e;
         }
-        hipError_t e = pcpd::launch_phase(ctx->n, ctx->buf[ctx->cur], ctx->buf[ctx->cur ^ 1],
-                                          ctx->d_lats, ctx->d_tiles, ctx->ntiles, sub, S, ctx->B,
-                                          ctx->shape, ctx->stream);
-        if (e == hipSuccess && ev) e = hipEventRecord(ev[1], ctx->stream);
-        if (e != hipSuccess) return e;
-        ctx->cur ^= 1;
-        sub += S;
     }
-    ctx->t += n_steps;
+    if (rel) {
+        hipError_t e = pcpd::launch_advance_clock(ctx->d_clock, rel, stream);
+        if (e != hipSuccess) return e;
+    }
+    *cur_out = cur;
     return hipSuccess;
 }
 
-hipError_t enqueue_density(pcpd_ctx *ctx, uint32_t slot) {
-    return pcpd::launch_density(ctx->buf[ctx->cur], ctx->d_lats, ctx->d_chunks, ctx->nchunks,
-                                ctx->d_counts + static_cast<size_t>(slot) * ctx->nlat, ctx->nlat,
-                                ctx->stream);
+// Capture a batch into an executable graph on the private capture stream.
+hipError_t capture_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops,
+                       pcpd_ctx::GraphEntry **out) {
+    hipError_t e = hipSuccess;
+    if (!ctx->cap_stream) {
+        e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    int cur_out = 0;
+    hipError_t e_enq = enqueue_ops(ctx, ops, ctx->cap_stream, false, &cur_out);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (e_enq != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e_enq;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    auto *g = new (std::nothrow) pcpd_ctx::GraphEntry();
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return hipErrorOutOfMemory;
+    }
+    g->ops = ops;
+    g->cur_in = ctx->cur;
+    g->cur_out = cur_out;
+    g->exec = exec;
+    if (ctx->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(ctx->graphs.front()->exec);
+        delete ctx->graphs.front();
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(g);
+    *out = g;
+    return hipSuccess;
+}
+
+// Run a batch: replay a cached graph of the same batch, capture one, or
+// launch directly (profiling on, or graphs off).
+hipError_t execute_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops) {
+    int cur = ctx->cur;
+    uint64_t steps = 0;
+    for (const BatchOp &op : ops) steps += op.steps;
+    if ((ctx->options & PCPD_OPT_GRAPH) && !ctx->profiling) {
+        pcpd_ctx::GraphEntry *g = nullptr;
+        for (auto *c : ctx->graphs)
+            if (c->cur_in == ctx->cur && c->ops == ops) g = c;
+        if (!g) {
+            hipError_t e = capture_ops(ctx, ops, &g);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
+        if (e != hipSuccess) return e;
+        cur = g->cur_out;
+    } else {
+        hipError_t e = enqueue_ops(ctx, ops, ctx->stream, ctx->profiling, &cur);
+        if (e != hipSuccess) return e;
+    }
+    ctx->cur = cur;
+    ctx->t += steps;
+    return hipSuccess;
 }
 
 void release(pcpd_ctx *ctx) {
@@ -235,6 +350,9 @@ void release(pcpd_ctx *ctx) {
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    drop_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->d_clock) (void)hipFree(ctx->d_clock);
     delete ctx;
 }
 
@@ -242,6 +360,89 @@ bool overflow_steps(uint64_t t, uint64_t steps, uint32_t B) {
     if (t + steps < t) return true;
     const uint64_t T = t + steps;
     return T > UINT64_MAX / B;
+}
+
+// Shapes the autotuner tries, and its process-wide cache keyed by what the
+// best shape depends on: model, block width and the sizes of the rings.
+using TuneKey = std::vector<uint64_t>;
+
+TuneKey tune_key(const pcpd_ctx *ctx) {
+    TuneKey k{static_cast<uint64_t>(ctx->n), ctx->B, ctx->nlat};
+    uint64_t total = 0, nbmax = 0, nbmin = UINT64_MAX;
+    for (const LatDesc &ld : ctx->lats) {
+        total += ld.nblocks;
+        nbmax = std::max<uint64_t>(nbmax, ld.nblocks);
+        nbmin = std::min<uint64_t>(nbmin, ld.nblocks);
+    }
+    k.push_back(total);
+    k.push_back(nbmax);
+    k.push_back(nbmin);
+    return k;
+}
+
+std::map<TuneKey, std::pair<PhaseShape, uint32_t>> &tune_cache() {
+    static std::map<TuneKey, std::pair<PhaseShape, uint32_t>> cache;
+    return cache;
+}
+
+// Time one phase launch of each candidate shape on the context's own lattice:
+// it reads the current copy and writes the spare one, so the state is left
+// untouched. Cost = kernel time per interior window-substep.
+hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t *best_pm) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return e;
+    uint64_t interior = 0;
+    for (const LatDesc &ld : ctx->lats) interior += ld.nblocks;
+    hipEvent_t ev[2];
+    if ((e = hipEventCreate(&ev[0])) != hipSuccess) return e;
+    if ((e = hipEventCreate(&ev[1])) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return e;
+    }
+    const PhaseShape keep_shape = ctx->shape;
+    const uint32_t keep_pm = ctx->phase_max;
+    double best_cost = 0.0;
+    bool found = false;
+    const uint32_t cols_list[] = {32, 48, 64, 96, 128, 160, 192, 256};
+    const uint32_t B = ctx->B;
+    const uint32_t pm_list[] = {B / 2, B, 2 * B, 3 * B, 4 * B};
+    for (uint32_t cols : cols_list) {
+        for (uint32_t pm : pm_list) {
+            PhaseShape sh{};
+            if (pm == 0 || pm > 512 || !make_shape(static_cast<uint32_t>(ctx->n), B, cols, pm, &sh))
+                continue;
+            ctx->shape = sh;
+            ctx->phase_max = pm;
+            if ((e = build_tiles(ctx)) != hipSuccess) break;
+            float ms = 0.0f;
+            for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) {
+                if (r == 1) e = hipEventRecord(ev[0], ctx->stream);
+                if (e == hipSuccess)
+                    e = pcpd::launch_phase(ctx->n, ctx->buf[ctx->cur], ctx->buf[ctx->cur ^ 1],
+                                           ctx->d_lats, ctx->d_tiles, ctx->ntiles, ctx->d_clock, 0,
+                                           pm, B, sh, ctx->stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) break;
+            const double cost = ms / (static_cast<double>(reps) * interior * pm);
+            if (!found || cost < best_cost) {
+                best_cost = cost;
+                *best = sh;
+                *best_pm = pm;
+                found = true;
+            }
+        }
+        if (e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    ctx->shape = keep_shape;
+    ctx->phase_max = keep_pm;
+    if (e == hipSuccess && !found) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = build_tiles(ctx);
+    return e;
 }
 
 }  // namespace
@@ -347,7 +548,14 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
         (e = hipMalloc(&ctx->d_chunks, chunks.size() * sizeof(DenChunk))) != hipSuccess ||
         (e = hipMemcpy(ctx->d_chunks, chunks.data(), chunks.size() * sizeof(DenChunk),
                        hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = build_tiles(ctx)) != hipSuccess || (e = ensure_count_slots(ctx, 1)) != hipSuccess) {
+        (e = build_tiles(ctx)) != hipSuccess || (e = ensure_count_slots(ctx, 1)) != hipSuccess ||
+        (e = hipMalloc(&ctx->d_clock, sizeof(uint64_t))) != hipSuccess) {
+        release(ctx);
+        return fail(nullptr, e);
+    }
+    const uint64_t sub0 = t0 * cfg->B;
+    e = hipMemcpy(ctx->d_clock, &sub0, sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
         release(ctx);
         return fail(nullptr, e);
     }
@@ -377,13 +585,14 @@ int pcpd_sweep(pcpd_ctx *ctx, uint64_t n_steps) {
     if (!ctx) return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
     if (overflow_steps(ctx->t, n_steps, ctx->B)) return PCPD_EOVERFLOW;
-    return fail(ctx, enqueue_sweep(ctx, n_steps));
+    if (n_steps == 0) return PCPD_OK;
+    return fail(ctx, execute_ops(ctx, {BatchOp{n_steps, -1}}));
 }
 
 int pcpd_density(pcpd_ctx *ctx, pcpd_counts *out) {
     if (!ctx || !out) return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
-    hipError_t e = enqueue_density(ctx, 0);
+    hipError_t e = execute_ops(ctx, {BatchOp{0, 0}});
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts, ctx->nlat * sizeof(Counts),
                            hipMemcpyDeviceToHost, ctx->stream);
@@ -401,10 +610,13 @@ int pcpd_run(pcpd_ctx *ctx, const uint64_t *times, uint32_t n_times, pcpd_counts
     }
     if (n_times && overflow_steps(times[n_times - 1], 0, ctx->B)) return PCPD_EOVERFLOW;
     hipError_t e = ensure_count_slots(ctx, n_times);
-    for (uint32_t r = 0; r < n_times && e == hipSuccess; ++r) {
-        e = enqueue_sweep(ctx, times[r] - ctx->t);
-        if (e == hipSuccess) e = enqueue_density(ctx, r);
+    std::vector<BatchOp> ops;
+    uint64_t at = ctx->t;
+    for (uint32_t r = 0; r < n_times; ++r) {
+        ops.push_back(BatchOp{times[r] - at, static_cast<int32_t>(r)});
+        at = times[r];
     }
+    if (e == hipSuccess && n_times) e = execute_ops(ctx, ops);
     if (e == hipSuccess && n_times)
         e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts,
                            static_cast<size_t>(n_times) * ctx->nlat * sizeof(Counts),
@@ -474,6 +686,42 @@ int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
     if (!ctx || !tuning) return PCPD_EINVAL;
     tuning->tile_cols = ctx->shape.cols;
     tuning->phase_max = ctx->phase_max;
+    return PCPD_OK;
+}
+
+int pcpd_set_options(pcpd_ctx *ctx, uint32_t options) {
+    if (!ctx || (options & ~static_cast<uint32_t>(PCPD_OPT_GRAPH))) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    ctx->options = options;
+    return PCPD_OK;
+}
+
+int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen) {
+    if (!ctx) return PCPD_EINVAL;
+    if (ctx->broken) return PCPD_ESTATE;
+    if (reps == 0) reps = 3;
+    TuneKey key = tune_key(ctx);
+    auto hit = tune_cache().find(key);
+    PhaseShape best{};
+    uint32_t best_pm = 0;
+    if (hit != tune_cache().end()) {
+        best = hit->second.first;
+        best_pm = hit->second.second;
+    } else {
+        hipError_t e = search_shape(ctx, reps, &best, &best_pm);
+        if (e != hipSuccess) return fail(ctx, e);
+        tune_cache()[key] = {best, best_pm};
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, e);
+    ctx->shape = best;
+    ctx->phase_max = best_pm;
+    e = build_tiles(ctx);
+    if (e != hipSuccess) return fail(ctx, e);
+    if (chosen) {
+        chosen->tile_cols = best.cols;
+        chosen->phase_max = best_pm;
+    }
     return PCPD_OK;
 }
 

@@ -57,9 +57,14 @@ struct PhaseShape {
     uint32_t hb;       // halo blocks on each side
 };
 
+// One phase: S substeps starting at substep *clock + s_off.
 hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
-                        const TileDesc *tiles, uint32_t ntiles, uint64_t s0, uint32_t S,
-                        uint32_t B, const PhaseShape &shape, hipStream_t stream);
+                        const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                        uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &shape,
+                        hipStream_t stream);
+
+// *clock += delta, on the device.
+hipError_t launch_advance_clock(uint64_t *clock, uint64_t delta, hipStream_t stream);
 
 hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream_t stream);
 

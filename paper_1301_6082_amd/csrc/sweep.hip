@@ -320,8 +320,13 @@ __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const
 template <int N>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-          const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles, uint64_t s0,
-          uint32_t S, uint32_t B, uint32_t hb, uint32_t cols, uint32_t ldw) {
+          const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
+          const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
+          uint32_t cols, uint32_t ldw) {
+    // first substep of the phase: the context's device clock plus this
+    // launch's offset, so that a captured sequence of launches is valid at
+    // any starting time
+    const uint64_t s0 = *clock + s_off;
     extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
     const TileDesc td = tiles[blockIdx.x];
     const LatDesc ld = lats[td.lat];
@@ -397,6 +402,10 @@ density_chunks(const uint64_t *__restrict__ buf, const LatDesc *__restrict__ lat
     }
 }
 
+__global__ void advance_clock(uint64_t *__restrict__ clock, uint64_t delta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *clock += delta;
+}
+
 __global__ void zero_counts(Counts *__restrict__ out, uint32_t nlat) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nlat) {
@@ -408,8 +417,9 @@ __global__ void zero_counts(Counts *__restrict__ out, uint32_t nlat) {
 
 template <int N>
 hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
-                          const TileDesc *tiles, uint32_t ntiles, uint64_t s0, uint32_t S,
-                          uint32_t B, const PhaseShape &sh, hipStream_t stream) {
+                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                          hipStream_t stream) {
     const size_t lds = phase_lds_bytes(B, sh.ldw, S);
     static bool attr_set = false;
     if (!attr_set) {
@@ -420,7 +430,7 @@ hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lat
         attr_set = true;
     }
     hipLaunchKernelGGL(brs_phase<N>, dim3(ntiles), dim3(sh.threads), lds, stream, src, dst, lats,
-                       tiles, s0, S, B, sh.hb, sh.cols, sh.ldw);
+                       tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
     return hipGetLastError();
 }
 
@@ -432,15 +442,21 @@ size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S) {
 }
 
 hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
-                        const TileDesc *tiles, uint32_t ntiles, uint64_t s0, uint32_t S,
-                        uint32_t B, const PhaseShape &shape, hipStream_t stream) {
+                        const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                        uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &shape,
+                        hipStream_t stream) {
     if (ntiles == 0 || S == 0) return hipSuccess;
     switch (n) {
-        case 1: return launch_phase_n<1>(src, dst, lats, tiles, ntiles, s0, S, B, shape, stream);
-        case 2: return launch_phase_n<2>(src, dst, lats, tiles, ntiles, s0, S, B, shape, stream);
-        case 3: return launch_phase_n<3>(src, dst, lats, tiles, ntiles, s0, S, B, shape, stream);
+        case 1: return launch_phase_n<1>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
+        case 2: return launch_phase_n<2>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
+        case 3: return launch_phase_n<3>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_advance_clock(uint64_t *clock, uint64_t delta, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_clock, dim3(1), dim3(64), 0, stream, clock, delta);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream_t stream) {

@@ -18,6 +18,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpcpd.so")
 
+OPT_GRAPH = 1
 PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
 DP, PCPD, TCPD = 1, 2, 3
 INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
@@ -49,7 +50,8 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcpd_run",
            "pcpd_get_lattice", "pcpd_set_lattice", "pcpd_time", "pcpd_sync",
-           "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_profile", "pcpd_profile_read",
+           "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_set_options", "pcpd_autotune",
+           "pcpd_profile", "pcpd_profile_read",
            "pcpd_free", "pcpd_strerror"]
 
 
@@ -71,6 +73,8 @@ def load_library(path: str = LIB_PATH):
         "pcpd_sync": ([vp], ctypes.c_int),
         "pcpd_set_tuning": ([vp, P(Tuning)], ctypes.c_int),
         "pcpd_get_tuning": ([vp, P(Tuning)], ctypes.c_int),
+        "pcpd_set_options": ([vp, u32], ctypes.c_int),
+        "pcpd_autotune": ([vp, u32, P(Tuning)], ctypes.c_int),
         "pcpd_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "pcpd_profile_read": ([vp, P(ctypes.c_double), P(u64)], ctypes.c_int),
         "pcpd_free": ([vp], ctypes.c_int),
@@ -205,6 +209,16 @@ class Sim:
     def get_tuning(self):
         tu = Tuning()
         _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
+        return int(tu.tile_cols), int(tu.phase_max)
+
+    def set_options(self, graph: bool = False):
+        """graph=True: capture each sweep/run batch into a HIP graph and replay it."""
+        _check(_lib.pcpd_set_options(self._ctx, OPT_GRAPH if graph else 0), "pcpd_set_options")
+
+    def autotune(self, reps: int = 3):
+        """Time candidate tile shapes on this lattice (state unchanged); returns the choice."""
+        tu = Tuning()
+        _check(_lib.pcpd_autotune(self._ctx, int(reps), ctypes.byref(tu)), "pcpd_autotune")
         return int(tu.tile_cols), int(tu.phase_max)
 
     def profile(self, enable: bool = True):

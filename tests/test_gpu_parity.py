@@ -225,3 +225,60 @@ def test_profiling_does_not_change_results(pcpd):
             else:
                 assert n == 0
     np.testing.assert_array_equal(out[0], out[1])
+
+
+def test_graph_replays_match_direct_launches(pcpd):
+    """PCPD_OPT_GRAPH: batches are captured once and replayed; every replay,
+    with eager work between replays, must equal direct launches."""
+    insts = [Instance(0.1, 0.3, 64 * 200, 0), Instance(0.22, 0.6, 64 * 37, 1)]
+    with pcpd.Sim(2, 64, 2, 4, insts) as g, pcpd.Sim(2, 64, 2, 4, insts) as d:
+        g.set_options(graph=True)
+        for rep in range(4):
+            t = g.time
+            sched = [t + 2, t + 4, t + 8]
+            cg, cd = g.run(sched), d.run(sched)
+            np.testing.assert_array_equal(cg, cd, err_msg=f"replay {rep}")
+            for i in range(2):
+                np.testing.assert_array_equal(g.get_lattice(i), d.get_lattice(i))
+            if rep == 1:
+                g.sweep(1)   # eager work between replays (flips the copy parity)
+                d.sweep(1)
+        assert g.time == d.time
+        final = [g.get_lattice(i) for i in range(2)]
+        T = g.time
+    keys, runs = oracle_runs(2, 64, 2, 4, insts, [T])
+    for (i, q), r in zip(keys, runs):
+        L = insts[i].L
+        np.testing.assert_array_equal(final[i][q * L:(q + 1) * L], r.words)
+
+
+def test_autotune_keeps_results(pcpd):
+    insts = [Instance(0.12, 0.4, 64 * 1500, 3), Instance(0.2, 0.1, 64 * 300, 4)]
+    with pcpd.Sim(2, 64, 1, 11, insts) as sim:
+        before = sim.get_lattice(0)
+        chosen = sim.autotune(reps=2)
+        assert sim.get_tuning() == chosen
+        np.testing.assert_array_equal(sim.get_lattice(0), before)   # trials leave the state
+        counts = sim.run([3, 6])
+        lat = [sim.get_lattice(i) for i in range(2)]
+    print(f"[autotune] chose {chosen}", flush=True)
+    keys, runs = oracle_runs(2, 64, 1, 11, insts, [3, 6])
+    for (i, q), r in zip(keys, runs):
+        np.testing.assert_array_equal(lat[i], r.words)
+        N, NP, alive = r.counts()
+        np.testing.assert_array_equal(counts[:, i, 0, 0], N)
+
+
+def test_batch_in_one_graph_launch_matches_instances_alone(pcpd):
+    """Instances of uneven L batched in one context and one graph launch per
+    run give the same lattices as each instance in a context of its own."""
+    c = wl.cfg3(count=24)
+    with pcpd.Sim(c.model, c.B, 1, c.seed, c.instances) as sim:
+        sim.set_options(graph=True)
+        batch = sim.run([5, 10])
+        lat = [sim.get_lattice(i) for i in range(len(c.instances))]
+    for i in (0, 5, 17, 23):
+        with pcpd.Sim(c.model, c.B, 1, c.seed, [c.instances[i]]) as alone:
+            a = alone.run([5, 10])
+            np.testing.assert_array_equal(alone.get_lattice(0), lat[i], err_msg=f"inst {i}")
+            np.testing.assert_array_equal(a[:, 0], batch[:, i])
