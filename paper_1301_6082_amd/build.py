@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpcpd.so")
-SOURCES = ["sweep.hip", "pcpd_api.hip"]
+SOURCES = ["sweep.hip", "pcpd_api.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 # hipcc flags: CDNA4 only; packed FP32 instructions disabled for all device code.

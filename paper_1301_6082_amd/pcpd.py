@@ -53,6 +53,9 @@ EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcp
            "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_set_options", "pcpd_autotune",
            "pcpd_profile", "pcpd_profile_read",
            "pcpd_free", "pcpd_strerror"]
+MLP_EXPORTS = ["pcpd_mlp_init", "pcpd_mlp_get_params", "pcpd_mlp_set_params", "pcpd_mlp_predict",
+               "pcpd_mlp_grads", "pcpd_mlp_train_step", "pcpd_mlp_free"]
+MLP_PARAMS = 33665
 
 
 def load_library(path: str = LIB_PATH):
@@ -79,6 +82,13 @@ def load_library(path: str = LIB_PATH):
         "pcpd_profile_read": ([vp, P(ctypes.c_double), P(u64)], ctypes.c_int),
         "pcpd_free": ([vp], ctypes.c_int),
         "pcpd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "pcpd_mlp_init": ([P(vp), u32, P(Device)], ctypes.c_int),
+        "pcpd_mlp_get_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
+        "pcpd_mlp_set_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
+        "pcpd_mlp_predict": ([vp, vp, u32, vp], ctypes.c_int),
+        "pcpd_mlp_grads": ([vp, vp, vp, vp, u32, P(ctypes.c_float), P(ctypes.c_float)], ctypes.c_int),
+        "pcpd_mlp_train_step": ([vp, vp, vp, vp, u32, ctypes.c_float, P(ctypes.c_float)], ctypes.c_int),
+        "pcpd_mlp_free": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +259,75 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _dev_f32(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """The density surrogate (include/pcpd_mlp.h): 3-128-128-128-1 GELU
+    network on log10 rho; inputs and targets are float32 CUDA tensors."""
+
+    def __init__(self, seed: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the surrogate needs a ROCm GPU; none is visible")
+        dev = Device()
+        dev.hip_stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self._net = ctypes.c_void_p()
+        _check(_lib.pcpd_mlp_init(ctypes.byref(self._net), int(seed), ctypes.byref(dev)),
+               "pcpd_mlp_init")
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.pcpd_mlp_get_params(self._net, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "pcpd_mlp_get_params")
+        return out
+
+    def set_params(self, theta) -> None:
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32))
+        if th.shape != (MLP_PARAMS,):
+            raise ValueError("parameter vector must hold 33665 values")
+        _check(_lib.pcpd_mlp_set_params(self._net, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "pcpd_mlp_set_params")
+
+    def predict(self, x: torch.Tensor) -> torch.Tensor:
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(_lib.pcpd_mlp_predict(self._net, _dev_f32(x, (n, 3), "x"), n,
+                                     ctypes.c_void_p(y.data_ptr())), "pcpd_mlp_predict")
+        return y
+
+    def grads(self, x, target, mask=None):
+        n = x.shape[0]
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        m = _dev_f32(mask, (n,), "mask") if mask is not None else None
+        _check(_lib.pcpd_mlp_grads(self._net, _dev_f32(x, (n, 3), "x"), _dev_f32(target, (n,), "target"),
+                                   m, n, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   ctypes.byref(loss)), "pcpd_mlp_grads")
+        return float(loss.value), g
+
+    def train_step(self, x, target, mask=None, lr: float = 1e-3, want_loss: bool = False):
+        n = x.shape[0]
+        loss = ctypes.c_float()
+        m = _dev_f32(mask, (n,), "mask") if mask is not None else None
+        _check(_lib.pcpd_mlp_train_step(self._net, _dev_f32(x, (n, 3), "x"),
+                                        _dev_f32(target, (n,), "target"), m, n, float(lr),
+                                        ctypes.byref(loss) if want_loss else None),
+               "pcpd_mlp_train_step")
+        return float(loss.value) if want_loss else None
+
+    def close(self):
+        if getattr(self, "_net", None) and self._net.value:
+            _lib.pcpd_mlp_free(self._net)
+            self._net = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

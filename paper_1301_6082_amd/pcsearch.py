@@ -1,0 +1,330 @@
+"""Search for the critical annihilation rate p_c (paper Sec. 2: active phase
+for p < p_c, inactive for p > p_c, p_c depends on d), by plain bisection on a
+p-grid and by bisection guided by the density surrogate.
+
+Every run is a GPU simulation through the C ABI; the surrogate only proposes
+where to run. Site updates are counted for every run (the ledger), so the two
+searches can be compared on the work they need to reach their bracket.
+
+Classification of a density curve rho(t_k) (the order parameter, Sec. 1),
+motivated by the power law at p_c and its corrections to scaling (Sec. 5.3):
+the effective exponent delta_eff = -d log rho / d log t is roughly constant
+at p_c, falls towards 0 in the active phase (rho saturates) and grows in the
+inactive phase (faster than any power law). A curve is inactive if all its
+samples died, or if delta_eff over the last half-decade of t exceeds both its
+value over the half-decade before and a floor of 0.05; otherwise active.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import workloads
+
+DELTA_FLOOR = 0.05
+TRUST_TOL = 0.05          # |delta log10 rho| beyond which the surrogate is not trusted
+
+
+def features(p, d, t):
+    """Surrogate inputs (p / 0.25, d, log10(t) / 6), float32 [..., 3]."""
+    p, d, t = np.broadcast_arrays(np.asarray(p, float), np.asarray(d, float), np.asarray(t, float))
+    return np.stack([p / 0.25, d, np.log10(t) / 6.0], axis=-1).astype(np.float32)
+
+
+def _slope(logt, logr):
+    A = np.stack([logt, np.ones_like(logt)], axis=1)
+    return float(np.linalg.lstsq(A, logr, rcond=None)[0][0])
+
+
+def delta_eff_windows(times, rho) -> Tuple[float, float]:
+    """delta_eff fitted over [T/10, T/sqrt(10)] and [T/sqrt(10), T]."""
+    t = np.asarray(times, float)
+    r = np.asarray(rho, float)
+    T = t[-1]
+    lt, lr = np.log10(t), np.log10(np.maximum(r, 1e-300))
+    a = (t >= T / 10.0 * 0.999) & (t <= T / math.sqrt(10.0) * 1.001)
+    b = t >= T / math.sqrt(10.0) * 0.999
+    return -_slope(lt[a], lr[a]), -_slope(lt[b], lr[b])
+
+
+def classify(times, rho) -> bool:
+    """True if the curve is inactive (p above the finite-time p_c)."""
+    r = np.asarray(rho, float)
+    if r[-1] <= 0.0:
+        return True
+    prev, last = delta_eff_windows(times, r)
+    return bool(last > prev and last > DELTA_FLOOR)
+
+
+@dataclass
+class Ledger:
+    runs: int = 0
+    site_updates: int = 0
+    path: List[Tuple[int, float, bool]] = field(default_factory=list)  # (grid index, p, inactive)
+
+
+@dataclass
+class RunSpec:
+    L: int = 1 << 18
+    planes: int = 4
+    steps: int = 1_000_000
+    records: int = 64
+    B: int = 64
+    model: int = workloads.PCPD
+
+    def times(self):
+        return workloads.log_times(self.steps, self.records)
+
+    def site_updates(self):
+        return 64 * self.planes * self.L * self.steps
+
+
+def simulate_curve(spec: RunSpec, p: float, d: float, seed: int, stream: int):
+    """One verification run on the GPU; returns (times, rho)."""
+    from . import pcpd
+
+    inst = [workloads.Instance(float(p), float(d), spec.L, int(stream))]
+    times = spec.times()
+    with pcpd.Sim(spec.model, spec.B, spec.planes, int(seed), inst) as sim:
+        c = sim.run(times)
+    N = c[:, 0, :, 0].astype(np.float64).sum(axis=1)
+    return np.asarray(times, float), N / (64.0 * spec.planes * spec.L)
+
+
+class Grid:
+    """2^bits points uniform on [lo, hi]; run (d_idx, i) uses seed 1000+d_idx and stream i,
+    so the class of a grid point is a fixed function of the point."""
+
+    def __init__(self, lo=0.02, hi=0.30, bits=10):
+        self.p = np.linspace(lo, hi, 1 << bits)
+
+    def __len__(self):
+        return len(self.p)
+
+
+def _evaluate(i, grid, d, d_idx, spec, ledger, cache, runner):
+    if i in cache:
+        return cache[i]
+    times, rho = runner(spec, grid.p[i], d, 1000 + d_idx, i)
+    ina = classify(times, rho)
+    ledger.runs += 1
+    ledger.site_updates += spec.site_updates()
+    ledger.path.append((i, float(grid.p[i]), ina))
+    cache[i] = (times, rho, ina)
+    return cache[i]
+
+
+def plain_bisect(d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
+                 lo: int = 0, hi: Optional[int] = None, cache=None):
+    """Midpoint bisection; the ends are taken as active (lo) and inactive (hi)."""
+    hi = len(grid) - 1 if hi is None else hi
+    ledger = Ledger()
+    cache = {} if cache is None else cache
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        _, _, ina = _evaluate(mid, grid, d, d_idx, spec, ledger, cache, runner)
+        if ina:
+            hi = mid
+        else:
+            lo = mid
+    return (lo, hi), ledger
+
+
+def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
+    """Surrogate curves log10 rho(p_j, d, t_k) and their classes for grid indices idx."""
+    import torch
+
+    times = np.asarray(spec.times(), float)
+    P = np.repeat(grid.p[np.asarray(idx)], len(times))
+    T = np.tile(times, len(idx))
+    x = torch.from_numpy(features(P, d, T)).cuda()
+    y = net.predict(x).cpu().numpy().astype(np.float64).reshape(len(idx), len(times))
+    cls = [classify(times, 10.0 ** y[k]) for k in range(len(idx))]
+    return y, np.array(cls, dtype=bool)
+
+
+def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
+                     lo: int = 0, hi: Optional[int] = None, cache=None, predictor=None):
+    """Bisection whose probes the surrogate proposes: the first grid point it
+    predicts inactive inside the bracket (or the last predicted active one if
+    that point is the upper end). Each probe is simulated; the simulation
+    decides the class. If a simulated curve departs from the prediction by more
+    than TRUST_TOL in log10 rho at the two latest half-decades, later probes
+    fall back to midpoints. `predictor(d, idx)` -> (log10 rho [len(idx), times],
+    classes) replaces the network (tests)."""
+    hi = len(grid) - 1 if hi is None else hi
+    ledger = Ledger()
+    cache = {} if cache is None else cache
+    predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
+    trusted = True
+    times = np.asarray(spec.times(), float)
+    late = times >= times[-1] / 10.0
+    while hi - lo > 1:
+        inner = list(range(lo + 1, hi))
+        probe = (lo + hi) // 2
+        pred = None
+        if trusted:
+            ys, cls = predictor(d, inner)
+            first = next((k for k, c in enumerate(cls) if c), None)
+            if first is None:
+                probe = hi - 1
+            else:
+                probe = inner[first]
+            pred = ys[inner.index(probe)]
+        _, rho, ina = _evaluate(probe, grid, d, d_idx, spec, ledger, cache, runner)
+        if pred is not None:
+            sim = np.log10(np.maximum(rho, 1e-300))
+            err = np.abs(sim[late] - pred[late]).max() if rho[-1] > 0 else np.inf
+            if err > TRUST_TOL:
+                trusted = False
+        if ina:
+            hi = probe
+        else:
+            lo = probe
+    return (lo, hi), ledger
+
+
+# --------------------------------------------------------------------------
+# training data from the simulator and training on the GPU
+
+
+def training_batch(count: int, spec: RunSpec, seed: int, d_values=(0.1, 0.5, 0.9),
+                   p_range=(0.05, 0.25), L_range=(1 << 14, 1 << 16)):
+    """Instances of one batched run (config-3 style: uneven L, d from a set,
+    p uniform), drawn from numpy default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(math.log2(L_range[0]), math.log2(L_range[1]), size=count)
+    ds = rng.choice(np.asarray(d_values, float), size=count)
+    ps = rng.uniform(p_range[0], p_range[1], size=count)
+    insts = [workloads.Instance(float(ps[i]), float(ds[i]), 64 * int(2.0 ** u[i] // 64), i)
+             for i in range(count)]
+    return insts
+
+
+def simulate_training_set(insts, spec: RunSpec, seed: int, graph: bool = True):
+    """One batched GPU run of all instances (one plane each) with records at
+    spec.times(); returns (features [n,3], log10 rho [n], mask [n], site updates)."""
+    from . import pcpd
+
+    times = spec.times()
+    with pcpd.Sim(spec.model, spec.B, 1, seed, insts) as sim:
+        sim.set_options(graph=graph)
+        c = sim.run(times)
+    N = c[:, :, 0, 0].astype(np.float64)                       # [times, inst]
+    L = np.array([i.L for i in insts], float)
+    rho = N / (64.0 * L[None, :])
+    P = np.array([i.p for i in insts], float)[None, :].repeat(len(times), 0)
+    D = np.array([i.d for i in insts], float)[None, :].repeat(len(times), 0)
+    T = np.asarray(times, float)[:, None].repeat(len(insts), 1)
+    x = features(P.ravel(), D.ravel(), T.ravel())
+    mask = (rho.ravel() > 0).astype(np.float32)
+    y = np.log10(np.where(rho.ravel() > 0, rho.ravel(), 1.0)).astype(np.float32)
+    su = int(sum(64 * i.L for i in insts) * spec.steps)
+    return x, y, mask, su
+
+
+def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-3,
+          seed: int = 0, log: Optional[Callable[[str], None]] = None):
+    """Minibatch Adam on the GPU; returns the final full-set loss."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    X = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    Y = torch.from_numpy(np.ascontiguousarray(y, np.float32)).cuda()
+    M = torch.from_numpy(np.ascontiguousarray(mask, np.float32)).cuda()
+    n = X.shape[0]
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        step_lr = lr * (0.5 * (1 + math.cos(math.pi * ep / epochs)) * 0.9 + 0.1)
+        for s in range(0, n, batch):
+            idx = perm[s:s + batch]
+            net.train_step(X[idx].contiguous(), Y[idx].contiguous(), M[idx].contiguous(), lr=step_lr)
+        if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+            log(f"epoch {ep}: loss {net.grads(X, Y, M)[0]:.5f}")
+    return net.grads(X, Y, M)[0]
+
+
+# --------------------------------------------------------------------------
+# end-to-end comparison
+
+
+def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int = 10,
+            train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
+            epochs: int = 150, seed: int = 2013, log=print):
+    """Train the surrogate on simulator curves (batched runs at the search's
+    horizon), then search p_c for each d both ways. Returns a summary dict;
+    training site updates are reported separately from the searches'."""
+    import time
+
+    from . import pcpd
+
+    spec = spec or RunSpec()
+    grid = Grid(bits=bits)
+    t0 = time.perf_counter()
+    xs, ys, ms, train_su = [], [], [], 0
+    for b in range(train_batches):
+        insts = training_batch(train_count, spec, seed + b, d_values=d_values, L_range=train_L)
+        x, y, m, su = simulate_training_set(insts, spec, seed + b)
+        xs.append(x), ys.append(y), ms.append(m)
+        train_su += su
+    x, y, m = np.concatenate(xs), np.concatenate(ys), np.concatenate(ms)
+    t_data = time.perf_counter() - t0
+    net = pcpd.Surrogate(seed=seed)
+    t1 = time.perf_counter()
+    loss = train(net, x, y, m, epochs=epochs, seed=seed, log=log)
+    t_train = time.perf_counter() - t1
+    out = {"spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps, "grid": len(grid),
+                    "p_range": [float(grid.p[0]), float(grid.p[-1])]},
+           "training": {"curves": int(train_batches * train_count), "rows": int(len(y)),
+                        "site_updates": train_su, "data_s": t_data, "train_s": t_train,
+                        "final_loss": loss},
+           "searches": []}
+    for d_idx, d in enumerate(d_values):
+        cache = {}
+        t2 = time.perf_counter()
+        pb, pl = plain_bisect(d, d_idx, grid, spec, cache=cache)
+        t3 = time.perf_counter()
+        sb, sl = surrogate_bisect(net, d, d_idx, grid, spec, cache={})
+        t4 = time.perf_counter()
+        rec = {"d": d, "plain": {"bracket": [float(grid.p[pb[0]]), float(grid.p[pb[1]])],
+                                 "idx": list(pb), "runs": pl.runs, "site_updates": pl.site_updates,
+                                 "s": t3 - t2},
+               "surrogate": {"bracket": [float(grid.p[sb[0]]), float(grid.p[sb[1]])],
+                             "idx": list(sb), "runs": sl.runs, "site_updates": sl.site_updates,
+                             "s": t4 - t3, "path": sl.path},
+               "same_bracket": pb == sb,
+               "gain": pl.site_updates / max(sl.site_updates, 1)}
+        log(f"d={d}: plain {pb} in {pl.runs} runs, surrogate {sb} in {sl.runs} runs")
+        out["searches"].append(rec)
+    net.close()
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="p_c search, plain vs surrogate-guided")
+    ap.add_argument("--L", type=int, default=1 << 18)
+    ap.add_argument("--planes", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=1_000_000)
+    ap.add_argument("--bits", type=int, default=10)
+    ap.add_argument("--train-count", type=int, default=512)
+    ap.add_argument("--train-batches", type=int, default=2)
+    ap.add_argument("--train-L", type=str, default="16384,65536")
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--d", type=str, default="0.1,0.5,0.9")
+    a = ap.parse_args(argv)
+    spec = RunSpec(L=a.L, planes=a.planes, steps=a.steps)
+    res = compare(tuple(float(v) for v in a.d.split(",")), spec, bits=a.bits,
+                  train_count=a.train_count, train_batches=a.train_batches,
+                  train_L=tuple(int(v) for v in a.train_L.split(",")), epochs=a.epochs,
+                  log=lambda s: print(s, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,11 +8,11 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pcpd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pcpd.h", "pcpd_mlp.h")]
 
 
 def declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"PCPD_API\s+[\w\s\*]*?\b(pcpd_\w+)\s*\(", text)))
 
 
@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol(mod):
     exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
     missing = [n for n in declared() if n not in exported]
     assert not missing, missing
-    assert sorted(mod.EXPORTS) == declared()
+    assert sorted(mod.EXPORTS + mod.MLP_EXPORTS) == declared()
     # nothing else with the pcpd_ prefix leaks out
     assert sorted(n for n in exported if n.startswith("pcpd_")) == declared()
 

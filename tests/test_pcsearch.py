@@ -1,0 +1,109 @@
+"""Host logic of the p_c search: the curve classifier and both bisections,
+driven by synthetic curves (no GPU)."""
+import numpy as np
+import pytest
+
+from paper_1301_6082_amd import pcsearch as ps
+from paper_1301_6082_amd import workloads
+
+
+T = 10**5
+TIMES = np.asarray(workloads.log_times(T), float)
+
+
+def curve(kind, p=0.0):
+    t = TIMES
+    if kind == "critical":
+        return 0.8 * t ** -0.2
+    if kind == "active":          # power law crossing over to a plateau
+        return np.maximum(0.8 * t ** -0.2, 0.05)
+    if kind == "active_smooth":
+        return 0.05 + 0.8 * t ** -0.5
+    if kind == "inactive":        # power law times a stretched exponential cut-off
+        return 0.8 * t ** -0.2 * np.exp(-(t / 3e3) ** 0.7)
+    if kind == "extinct":
+        r = 0.8 * t ** -0.2
+        r[t > 1e4] = 0.0
+        return r
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind,inactive", [("critical", False), ("active", False),
+                                           ("active_smooth", False), ("inactive", True),
+                                           ("extinct", True)])
+def test_classifier_on_synthetic_curves(kind, inactive):
+    assert ps.classify(TIMES, curve(kind)) is inactive
+
+
+def test_noisy_plateau_is_active():
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        r = 0.3 * (1 + 1e-3 * rng.normal(size=TIMES.size))
+        assert not ps.classify(TIMES, r)
+
+
+def test_delta_eff_of_a_power_law():
+    a, b = ps.delta_eff_windows(TIMES, 2.0 * TIMES ** -0.37)
+    assert abs(a - 0.37) < 1e-9 and abs(b - 0.37) < 1e-9
+
+
+def _fake_runner(flip):
+    """Class of grid point i: inactive iff i >= flip; the curve encodes it."""
+    def run(spec, p, d, seed, stream):
+        return TIMES, curve("inactive" if stream >= flip else "active")
+    return run
+
+
+SPEC = ps.RunSpec(L=1 << 10, planes=1, steps=T)
+
+
+@pytest.mark.parametrize("flip", [1, 2, 300, 511, 512, 1023])
+def test_plain_bisection_finds_the_flip_in_log2_runs(flip):
+    grid = ps.Grid(bits=10)
+    (lo, hi), led = ps.plain_bisect(0.5, 1, grid, SPEC, runner=_fake_runner(flip))
+    assert (lo, hi) == (flip - 1, flip)
+    assert led.runs <= 10 and led.site_updates == led.runs * SPEC.site_updates()
+
+
+def _predictor(flip_pred, offset=0.0):
+    def pred(d, idx):
+        ys = np.array([np.log10(curve("inactive" if i >= flip_pred else "active")) + offset
+                       for i in idx])
+        return ys, np.array([i >= flip_pred for i in idx])
+    return pred
+
+
+@pytest.mark.parametrize("flip", [2, 300, 777, 1023])
+def test_exact_surrogate_needs_two_runs(flip):
+    grid = ps.Grid(bits=10)
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
+                                        predictor=_predictor(flip))
+    assert (lo, hi) == (flip - 1, flip)
+    assert led.runs <= 2
+
+
+def test_biased_surrogate_still_reaches_the_same_bracket():
+    grid = ps.Grid(bits=10)
+    flip = 400
+    plain, pl = ps.plain_bisect(0.5, 1, grid, SPEC, runner=_fake_runner(flip))
+    for shift in (-40, -3, 5, 60):
+        (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
+                                            predictor=_predictor(flip + shift))
+        assert (lo, hi) == plain
+
+
+def test_untrusted_surrogate_falls_back_to_midpoints():
+    grid = ps.Grid(bits=10)
+    flip = 400
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
+                                        predictor=_predictor(flip + 200, offset=0.5))
+    assert (lo, hi) == (flip - 1, flip)
+    assert led.runs <= 11
+    # after the first probe every probe is a midpoint of the current bracket
+    probes = [i for i, _, _ in led.path]
+    assert probes[0] == 600
+
+
+def test_features():
+    x = ps.features([0.25, 0.125], [0.5, 0.1], [1.0, 1e6])
+    np.testing.assert_allclose(x, [[1.0, 0.5, 0.0], [0.5, 0.1, 1.0]], rtol=1e-6)
