@@ -9,10 +9,12 @@ searches can be compared on the work they need to reach their bracket.
 Classification of a density curve rho(t_k) (the order parameter, Sec. 1),
 motivated by the power law at p_c and its corrections to scaling (Sec. 5.3):
 the effective exponent delta_eff = -d log rho / d log t is roughly constant
-at p_c, falls towards 0 in the active phase (rho saturates) and grows in the
-inactive phase (faster than any power law). A curve is inactive if all its
-samples died, or if delta_eff over the last half-decade of t exceeds both its
-value over the half-decade before and a floor of 0.05; otherwise active.
+at p_c (about 0.2 for PCPD), falls towards 0 in the active phase (rho
+saturates) and rises in the inactive phase towards the 1/2 of diffusing,
+pair-annihilating particles (pairs vanish quickly; lone particles only meet
+by diffusion). A curve is inactive if all its samples died, or if delta_eff
+over the last half-decade of t is above DELTA_HIGH, or if it exceeds both its
+value over the half-decade before and DELTA_FLOOR; otherwise active.
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ import numpy as np
 from . import workloads
 
 DELTA_FLOOR = 0.05
+DELTA_HIGH = 0.35
 TRUST_TOL = 0.05          # |delta log10 rho| beyond which the surrogate is not trusted
 
 
@@ -56,14 +59,15 @@ def classify(times, rho) -> bool:
     if r[-1] <= 0.0:
         return True
     prev, last = delta_eff_windows(times, r)
-    return bool(last > prev and last > DELTA_FLOOR)
+    return bool(last > DELTA_HIGH or (last > prev and last > DELTA_FLOOR))
 
 
 @dataclass
 class Ledger:
     runs: int = 0
     site_updates: int = 0
-    path: List[Tuple[int, float, bool]] = field(default_factory=list)  # (grid index, p, inactive)
+    # (grid index, p, inactive, delta_eff previous half-decade, last half-decade, rho(T))
+    path: List[Tuple] = field(default_factory=list)
 
 
 @dataclass
@@ -95,8 +99,10 @@ def simulate_curve(spec: RunSpec, p: float, d: float, seed: int, stream: int):
 
 
 class Grid:
-    """2^bits points uniform on [lo, hi]; run (d_idx, i) uses seed 1000+d_idx and stream i,
-    so the class of a grid point is a fixed function of the point."""
+    """2^bits points uniform on [lo, hi]. Every run at diffusion index d_idx
+    uses seed 1000 + d_idx and stream 0 (common random numbers across the
+    grid): the class of a grid point is a fixed function of the point, and
+    neighbouring points see the same draws, so classes change smoothly with p."""
 
     def __init__(self, lo=0.02, hi=0.30, bits=10):
         self.p = np.linspace(lo, hi, 1 << bits)
@@ -108,11 +114,12 @@ class Grid:
 def _evaluate(i, grid, d, d_idx, spec, ledger, cache, runner):
     if i in cache:
         return cache[i]
-    times, rho = runner(spec, grid.p[i], d, 1000 + d_idx, i)
+    times, rho = runner(spec, grid.p[i], d, 1000 + d_idx, 0)
     ina = classify(times, rho)
     ledger.runs += 1
     ledger.site_updates += spec.site_updates()
-    ledger.path.append((i, float(grid.p[i]), ina))
+    dp, dl = delta_eff_windows(times, rho) if rho[-1] > 0 else (float("nan"), float("nan"))
+    ledger.path.append((i, float(grid.p[i]), ina, round(dp, 4), round(dl, 4), float(rho[-1])))
     cache[i] = (times, rho, ina)
     return cache[i]
 
@@ -152,9 +159,10 @@ def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_c
     predicts inactive inside the bracket (or the last predicted active one if
     that point is the upper end). Each probe is simulated; the simulation
     decides the class. If a simulated curve departs from the prediction by more
-    than TRUST_TOL in log10 rho at the two latest half-decades, later probes
-    fall back to midpoints. `predictor(d, idx)` -> (log10 rho [len(idx), times],
-    classes) replaces the network (tests)."""
+    than TRUST_TOL in log10 rho over the last decade of t, or its class
+    contradicts the predicted class, later probes fall back to midpoints.
+    `predictor(d, idx)` -> (log10 rho [len(idx), times], classes) replaces the
+    network (tests)."""
     hi = len(grid) - 1 if hi is None else hi
     ledger = Ledger()
     cache = {} if cache is None else cache
@@ -165,7 +173,7 @@ def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_c
     while hi - lo > 1:
         inner = list(range(lo + 1, hi))
         probe = (lo + hi) // 2
-        pred = None
+        pred = pred_cls = None
         if trusted:
             ys, cls = predictor(d, inner)
             first = next((k for k, c in enumerate(cls) if c), None)
@@ -174,11 +182,12 @@ def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_c
             else:
                 probe = inner[first]
             pred = ys[inner.index(probe)]
+            pred_cls = bool(cls[inner.index(probe)])
         _, rho, ina = _evaluate(probe, grid, d, d_idx, spec, ledger, cache, runner)
         if pred is not None:
             sim = np.log10(np.maximum(rho, 1e-300))
             err = np.abs(sim[late] - pred[late]).max() if rho[-1] > 0 else np.inf
-            if err > TRUST_TOL:
+            if err > TRUST_TOL or ina != pred_cls:
                 trusted = False
         if ina:
             hi = probe

@@ -21,6 +21,8 @@ def curve(kind, p=0.0):
         return 0.05 + 0.8 * t ** -0.5
     if kind == "inactive":        # power law times a stretched exponential cut-off
         return 0.8 * t ** -0.2 * np.exp(-(t / 3e3) ** 0.7)
+    if kind == "diffusive":       # inactive phase: lone particles annihilate by diffusion
+        return 0.3 * (1 + t / 50.0) ** -0.5
     if kind == "extinct":
         r = 0.8 * t ** -0.2
         r[t > 1e4] = 0.0
@@ -30,6 +32,7 @@ def curve(kind, p=0.0):
 
 @pytest.mark.parametrize("kind,inactive", [("critical", False), ("active", False),
                                            ("active_smooth", False), ("inactive", True),
+                                           ("diffusive", True),
                                            ("extinct", True)])
 def test_classifier_on_synthetic_curves(kind, inactive):
     assert ps.classify(TIMES, curve(kind)) is inactive
@@ -49,8 +52,11 @@ def test_delta_eff_of_a_power_law():
 
 def _fake_runner(flip):
     """Class of grid point i: inactive iff i >= flip; the curve encodes it."""
+    grid = ps.Grid(bits=10)
+
     def run(spec, p, d, seed, stream):
-        return TIMES, curve("inactive" if stream >= flip else "active")
+        i = int(np.argmin(np.abs(grid.p - p)))
+        return TIMES, curve("inactive" if i >= flip else "active")
     return run
 
 
@@ -100,8 +106,19 @@ def test_untrusted_surrogate_falls_back_to_midpoints():
     assert (lo, hi) == (flip - 1, flip)
     assert led.runs <= 11
     # after the first probe every probe is a midpoint of the current bracket
-    probes = [i for i, _, _ in led.path]
+    probes = [e[0] for e in led.path]
     assert probes[0] == 600
+
+
+def test_contradicted_surrogate_stops_walking():
+    """A surrogate biased low keeps predicting the next point inactive; the
+    first contradiction must end its proposals (no linear walk)."""
+    grid = ps.Grid(bits=10)
+    flip = 700
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
+                                        predictor=_predictor(30))
+    assert (lo, hi) == (flip - 1, flip)
+    assert led.runs <= 11
 
 
 def test_features():
