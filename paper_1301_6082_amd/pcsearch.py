@@ -28,7 +28,6 @@ from . import workloads
 
 DELTA_FLOOR = 0.05
 DELTA_HIGH = 0.35
-TRUST_TOL = 0.05          # |delta log10 rho| beyond which the surrogate is not trusted
 
 
 def features(p, d, t):
@@ -153,46 +152,75 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
     return y, np.array(cls, dtype=bool)
 
 
+CALIBRATED_PROBES = 4     # probes placed by the calibrated surrogate before midpoints
+
+
+def match_index(ys, sim_log10, late) -> int:
+    """Grid index whose predicted curve is closest (mean |log10 rho| gap over
+    the late times) to a simulated curve."""
+    err = np.mean(np.abs(ys[:, late] - sim_log10[late]), axis=1)
+    return int(np.argmin(err))
+
+
 def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
-                     lo: int = 0, hi: Optional[int] = None, cache=None, predictor=None):
-    """Bisection whose probes the surrogate proposes: the first grid point it
-    predicts inactive inside the bracket (or the last predicted active one if
-    that point is the upper end). Each probe is simulated; the simulation
-    decides the class. If a simulated curve departs from the prediction by more
-    than TRUST_TOL in log10 rho over the last decade of t, or its class
-    contradicts the predicted class, later probes fall back to midpoints.
-    `predictor(d, idx)` -> (log10 rho [len(idx), times], classes) replaces the
-    network (tests)."""
+                     lo: int = 0, hi: Optional[int] = None, cache=None, predictor=None,
+                     calibrated: int = CALIBRATED_PROBES):
+    """Bracket search whose probes the surrogate places. The surrogate's curves
+    for the whole grid give its flip f0 (first grid point it predicts inactive
+    inside the bracket). Each simulated probe calibrates it: the grid index j
+    whose predicted curve best matches the simulated one over the last decade
+    of t is where the surrogate puts that curve, so its flip is moved by
+    (probe - j). The next probe is the calibrated flip, or the point below it
+    when the flip is already the upper end of the bracket; when the estimate
+    keeps pressing against an end of the bracket the step from that end
+    doubles. After `calibrated` such probes, or after an extinct run (which
+    calibrates nothing), probes are midpoints. The simulation decides every
+    class. `predictor(d, idx)` -> (log10 rho [len(idx), times], classes)
+    replaces the network (tests)."""
     hi = len(grid) - 1 if hi is None else hi
     ledger = Ledger()
     cache = {} if cache is None else cache
     predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
-    trusted = True
     times = np.asarray(spec.times(), float)
     late = times >= times[-1] / 10.0
+    ys, cls = predictor(d, list(range(len(grid))))
+    ys = np.asarray(ys, float)
+    cls = np.asarray(cls, bool)
+    inside = np.nonzero(cls[lo + 1:hi + 1])[0]
+    f0 = lo + 1 + int(inside[0]) if inside.size else hi
+    shift, placed, streak, last_end = 0, 0, 0, None
     while hi - lo > 1:
-        inner = list(range(lo + 1, hi))
-        probe = (lo + hi) // 2
-        pred = pred_cls = None
-        if trusted:
-            ys, cls = predictor(d, inner)
-            first = next((k for k, c in enumerate(cls) if c), None)
-            if first is None:
-                probe = hi - 1
+        by_surrogate = placed < calibrated
+        if by_surrogate:
+            f = f0 + shift
+            if f >= hi:
+                end = "hi"
+            elif f <= lo + 1:
+                end = "lo"
             else:
-                probe = inner[first]
-            pred = ys[inner.index(probe)]
-            pred_cls = bool(cls[inner.index(probe)])
+                end = None
+            streak = streak + 1 if (end is not None and end == last_end) else 0
+            last_end = end
+            step = 1 << streak
+            if end == "hi":
+                probe = max(hi - step, lo + 1)
+            elif end == "lo":
+                probe = min(lo + step, hi - 1)
+            else:
+                probe = f
+            placed += 1
+        else:
+            probe = (lo + hi) // 2
         _, rho, ina = _evaluate(probe, grid, d, d_idx, spec, ledger, cache, runner)
-        if pred is not None:
-            sim = np.log10(np.maximum(rho, 1e-300))
-            err = np.abs(sim[late] - pred[late]).max() if rho[-1] > 0 else np.inf
-            if err > TRUST_TOL or ina != pred_cls:
-                trusted = False
         if ina:
             hi = probe
         else:
             lo = probe
+        if by_surrogate:
+            if rho[-1] > 0:
+                shift = probe - match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
+            else:
+                placed = calibrated  # extinct: no calibration, midpoints from here on
     return (lo, hi), ledger
 
 
@@ -260,18 +288,16 @@ def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-
 # end-to-end comparison
 
 
-def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int = 10,
-            train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
-            epochs: int = 150, seed: int = 2013, log=print):
-    """Train the surrogate on simulator curves (batched runs at the search's
-    horizon), then search p_c for each d both ways. Returns a summary dict;
-    training site updates are reported separately from the searches'."""
+def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
+                    train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
+                    epochs: int = 150, seed: int = 2013, log=print):
+    """Simulate the training curves (batched runs at the search's horizon) and
+    train a surrogate on them. Returns (net, training summary)."""
     import time
 
     from . import pcpd
 
     spec = spec or RunSpec()
-    grid = Grid(bits=bits)
     t0 = time.perf_counter()
     xs, ys, ms, train_su = [], [], [], 0
     for b in range(train_batches):
@@ -285,30 +311,51 @@ def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int 
     t1 = time.perf_counter()
     loss = train(net, x, y, m, epochs=epochs, seed=seed, log=log)
     t_train = time.perf_counter() - t1
+    return net, {"curves": int(train_batches * train_count), "rows": int(len(y)),
+                 "site_updates": train_su, "data_s": t_data, "train_s": t_train,
+                 "final_loss": loss}
+
+
+def search_pair(net, d, d_idx, spec: RunSpec, grid: Grid, log=print):
+    """Plain and surrogate-guided searches at one d, each with its own ledger
+    and cache (no run is shared between them)."""
+    import time
+
+    t2 = time.perf_counter()
+    pb, pl = plain_bisect(d, d_idx, grid, spec, cache={})
+    t3 = time.perf_counter()
+    sb, sl = surrogate_bisect(net, d, d_idx, grid, spec, cache={})
+    t4 = time.perf_counter()
+    log(f"d={d}: plain {pb} in {pl.runs} runs, surrogate {sb} in {sl.runs} runs")
+    return {"d": d,
+            "plain": {"bracket": [float(grid.p[pb[0]]), float(grid.p[pb[1]])], "idx": list(pb),
+                      "runs": pl.runs, "site_updates": pl.site_updates, "s": t3 - t2,
+                      "path": pl.path},
+            "surrogate": {"bracket": [float(grid.p[sb[0]]), float(grid.p[sb[1]])],
+                          "idx": list(sb), "runs": sl.runs, "site_updates": sl.site_updates,
+                          "s": t4 - t3, "path": sl.path},
+            "same_bracket": pb == sb,
+            "gain": pl.site_updates / max(sl.site_updates, 1)}
+
+
+def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int = 10,
+            train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
+            epochs: int = 150, seed: int = 2013, log=print):
+    """Train the surrogate on simulator curves, then search p_c for each d both
+    ways. Returns a summary dict; training site updates are reported
+    separately from the searches'."""
+    spec = spec or RunSpec()
+    grid = Grid(bits=bits)
+    net, training = build_surrogate(d_values, spec, train_count, train_batches, train_L,
+                                    epochs, seed, log)
     out = {"spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps, "grid": len(grid),
                     "p_range": [float(grid.p[0]), float(grid.p[-1])]},
-           "training": {"curves": int(train_batches * train_count), "rows": int(len(y)),
-                        "site_updates": train_su, "data_s": t_data, "train_s": t_train,
-                        "final_loss": loss},
-           "searches": []}
-    for d_idx, d in enumerate(d_values):
-        cache = {}
-        t2 = time.perf_counter()
-        pb, pl = plain_bisect(d, d_idx, grid, spec, cache=cache)
-        t3 = time.perf_counter()
-        sb, sl = surrogate_bisect(net, d, d_idx, grid, spec, cache={})
-        t4 = time.perf_counter()
-        rec = {"d": d, "plain": {"bracket": [float(grid.p[pb[0]]), float(grid.p[pb[1]])],
-                                 "idx": list(pb), "runs": pl.runs, "site_updates": pl.site_updates,
-                                 "s": t3 - t2},
-               "surrogate": {"bracket": [float(grid.p[sb[0]]), float(grid.p[sb[1]])],
-                             "idx": list(sb), "runs": sl.runs, "site_updates": sl.site_updates,
-                             "s": t4 - t3, "path": sl.path},
-               "same_bracket": pb == sb,
-               "gain": pl.site_updates / max(sl.site_updates, 1)}
-        log(f"d={d}: plain {pb} in {pl.runs} runs, surrogate {sb} in {sl.runs} runs")
-        out["searches"].append(rec)
-    net.close()
+           "training": training, "searches": []}
+    try:
+        for d_idx, d in enumerate(d_values):
+            out["searches"].append(search_pair(net, d, d_idx, spec, grid, log))
+    finally:
+        net.close()
     return out
 
 
@@ -326,12 +373,38 @@ def main(argv=None):
     ap.add_argument("--train-L", type=str, default="16384,65536")
     ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--d", type=str, default="0.1,0.5,0.9")
+    ap.add_argument("--d-index", type=str, default=None,
+                    help="comma-separated indices into --d to search (default: all)")
+    ap.add_argument("--save-net", type=str, default=None, help="write trained parameters (.npy)")
+    ap.add_argument("--load-net", type=str, default=None, help="read parameters, skip training")
+    ap.add_argument("--train-only", action="store_true")
     a = ap.parse_args(argv)
+    from . import pcpd
+
+    log = lambda s: print(s, flush=True)  # noqa: E731
     spec = RunSpec(L=a.L, planes=a.planes, steps=a.steps)
-    res = compare(tuple(float(v) for v in a.d.split(",")), spec, bits=a.bits,
-                  train_count=a.train_count, train_batches=a.train_batches,
-                  train_L=tuple(int(v) for v in a.train_L.split(",")), epochs=a.epochs,
-                  log=lambda s: print(s, flush=True))
+    grid = Grid(bits=a.bits)
+    d_values = tuple(float(v) for v in a.d.split(","))
+    res = {"spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps, "grid": len(grid),
+                    "p_range": [float(grid.p[0]), float(grid.p[-1])]},
+           "training": None, "searches": []}
+    if a.load_net:
+        net = pcpd.Surrogate(seed=0)
+        net.set_params(np.load(a.load_net))
+    else:
+        net, res["training"] = build_surrogate(
+            d_values, spec, a.train_count, a.train_batches,
+            tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log)
+        print(json.dumps({"training": res["training"]}), flush=True)
+    if a.save_net:
+        np.save(a.save_net, net.params())
+    if not a.train_only:
+        keep = range(len(d_values)) if a.d_index is None else [int(v) for v in a.d_index.split(",")]
+        for k in keep:
+            r = search_pair(net, d_values[k], k, spec, grid, log)
+            res["searches"].append(r)
+            print(json.dumps({"search": r}), flush=True)
+    net.close()
     print(json.dumps(res), flush=True)
 
 

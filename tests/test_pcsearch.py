@@ -98,27 +98,83 @@ def test_biased_surrogate_still_reaches_the_same_bracket():
         assert (lo, hi) == plain
 
 
-def test_untrusted_surrogate_falls_back_to_midpoints():
-    grid = ps.Grid(bits=10)
-    flip = 400
-    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
-                                        predictor=_predictor(flip + 200, offset=0.5))
-    assert (lo, hi) == (flip - 1, flip)
-    assert led.runs <= 11
-    # after the first probe every probe is a midpoint of the current bracket
-    probes = [e[0] for e in led.path]
-    assert probes[0] == 600
-
-
 def test_contradicted_surrogate_stops_walking():
-    """A surrogate biased low keeps predicting the next point inactive; the
-    first contradiction must end its proposals (no linear walk)."""
+    """A surrogate biased far low (its flip at 30, the true one at 700) and
+    whose active curves are all alike cannot calibrate; its placed probes end
+    after CALIBRATED_PROBES and midpoints close the bracket."""
     grid = ps.Grid(bits=10)
     flip = 700
     (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_fake_runner(flip),
                                         predictor=_predictor(30))
     assert (lo, hi) == (flip - 1, flip)
-    assert led.runs <= 11
+    assert led.runs <= ps.CALIBRATED_PROBES + 10
+
+
+# A family of curves that changes smoothly with the grid index: active below
+# the flip F (power law plus a plateau growing with the distance), inactive
+# from F on (power law times a stretched exponential whose time scale shrinks
+# with the distance). The classifier puts the flip exactly at F.
+def family(i, F):
+    x = (i - F + 0.5) / 40.0
+    t = TIMES
+    if x < 0:
+        return 0.8 * t ** -0.2 + 0.1 * (-x) ** 0.5
+    return 0.8 * t ** -0.2 * np.exp(-(t * x / 2e3) ** 0.7)
+
+
+def _family_runner(F):
+    grid = ps.Grid(bits=10)
+
+    def run(spec, p, d, seed, stream):
+        i = int(np.argmin(np.abs(grid.p - p)))
+        return TIMES, family(i, F)
+    return run
+
+
+def _family_predictor(F):
+    def pred(d, idx):
+        ys = np.array([np.log10(np.maximum(family(i, F), 1e-300)) for i in idx])
+        return ys, np.array([ps.classify(TIMES, family(i, F)) for i in idx])
+    return pred
+
+
+@pytest.mark.parametrize("F", [40, 333, 700])
+def test_family_flips_where_stated(F):
+    cls = [ps.classify(TIMES, family(i, F)) for i in range(F - 30, F + 30)]
+    assert cls == [False] * 30 + [True] * 30
+
+
+@pytest.mark.parametrize("F,bias", [(333, 0), (333, 7), (333, -25), (700, 40), (120, -60)])
+def test_shifted_surrogate_is_calibrated_by_one_run(F, bias):
+    """A surrogate whose curves are the true ones shifted by `bias` grid
+    points: the first probe calibrates it, so at most three runs close the
+    bracket (two when it is exact)."""
+    grid = ps.Grid(bits=10)
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_family_runner(F),
+                                        predictor=_family_predictor(F + bias))
+    assert (lo, hi) == (F - 1, F)
+    assert led.runs <= (2 if bias == 0 else 3)
+    (plo, phi), pl = ps.plain_bisect(0.5, 1, grid, SPEC, runner=_family_runner(F))
+    assert (plo, phi) == (lo, hi) and pl.runs == 10
+
+
+def test_unrelated_surrogate_still_closes_the_bracket():
+    grid = ps.Grid(bits=10)
+    rng = np.random.default_rng(3)
+
+    def garbage(d, idx):
+        return rng.normal(size=(len(idx), TIMES.size)), rng.random(len(idx)) < 0.5
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_family_runner(512),
+                                        predictor=garbage)
+    assert (lo, hi) == (511, 512)
+    assert led.runs <= ps.CALIBRATED_PROBES + 10
+
+
+def test_match_index_finds_the_nearest_curve():
+    ys = np.stack([np.log10(family(i, 300)) for i in range(0, 600, 3)])
+    late = TIMES >= TIMES[-1] / 10
+    for k in (5, 90, 150):
+        assert ps.match_index(ys, ys[k] + 1e-4, late) == k
 
 
 def test_features():
