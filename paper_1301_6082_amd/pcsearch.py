@@ -85,23 +85,35 @@ class RunSpec:
         return 64 * self.planes * self.L * self.steps
 
 
-def simulate_curve(spec: RunSpec, p: float, d: float, seed: int, stream: int):
-    """One verification run on the GPU; returns (times, rho)."""
+SEED = 1000  # Philox key word 0 of every verification run; the stream id is d's index
+
+
+def simulate_curves(spec: RunSpec, probes: Sequence[Tuple[float, float, int]]):
+    """Verification runs of several (p, d, stream) probes as one batched GPU
+    run (each instance is simulated exactly as it would be alone); returns
+    (times, [rho per probe])."""
     from . import pcpd
 
-    inst = [workloads.Instance(float(p), float(d), spec.L, int(stream))]
+    insts = [workloads.Instance(float(p), float(d), spec.L, int(st)) for p, d, st in probes]
     times = spec.times()
-    with pcpd.Sim(spec.model, spec.B, spec.planes, int(seed), inst) as sim:
+    with pcpd.Sim(spec.model, spec.B, spec.planes, SEED, insts) as sim:
         c = sim.run(times)
-    N = c[:, 0, :, 0].astype(np.float64).sum(axis=1)
-    return np.asarray(times, float), N / (64.0 * spec.planes * spec.L)
+    N = c[:, :, :, 0].astype(np.float64).sum(axis=2)           # [times, instance]
+    rho = N / (64.0 * spec.planes * spec.L)
+    return np.asarray(times, float), [rho[:, k] for k in range(len(insts))]
+
+
+def simulate_curve(spec: RunSpec, p: float, d: float, stream: int):
+    """One verification run on the GPU; returns (times, rho)."""
+    times, rhos = simulate_curves(spec, [(p, d, stream)])
+    return times, rhos[0]
 
 
 class Grid:
     """2^bits points uniform on [lo, hi]. Every run at diffusion index d_idx
-    uses seed 1000 + d_idx and stream 0 (common random numbers across the
-    grid): the class of a grid point is a fixed function of the point, and
-    neighbouring points see the same draws, so classes change smoothly with p."""
+    uses key (SEED, d_idx): common random numbers across the grid, so the
+    class of a grid point is a fixed function of the point and neighbouring
+    points see the same draws (classes change smoothly with p)."""
 
     def __init__(self, lo=0.02, hi=0.30, bits=10):
         self.p = np.linspace(lo, hi, 1 << bits)
@@ -110,33 +122,137 @@ class Grid:
         return len(self.p)
 
 
-def _evaluate(i, grid, d, d_idx, spec, ledger, cache, runner):
-    if i in cache:
-        return cache[i]
-    times, rho = runner(spec, grid.p[i], d, 1000 + d_idx, 0)
-    ina = classify(times, rho)
+# Searches are generators: they yield the grid index to simulate next and
+# receive (times, rho, inactive); they return the final bracket. Each keeps
+# its own ledger and cache, so two searches never share a run.
+
+
+def _record(ledger, grid, i, times, rho, ina, spec):
     ledger.runs += 1
     ledger.site_updates += spec.site_updates()
     dp, dl = delta_eff_windows(times, rho) if rho[-1] > 0 else (float("nan"), float("nan"))
     ledger.path.append((i, float(grid.p[i]), ina, round(dp, 4), round(dl, 4), float(rho[-1])))
-    cache[i] = (times, rho, ina)
-    return cache[i]
 
 
-def plain_bisect(d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
-                 lo: int = 0, hi: Optional[int] = None, cache=None):
+def plain_steps(grid: Grid, lo: int, hi: int):
     """Midpoint bisection; the ends are taken as active (lo) and inactive (hi)."""
-    hi = len(grid) - 1 if hi is None else hi
-    ledger = Ledger()
-    cache = {} if cache is None else cache
     while hi - lo > 1:
         mid = (lo + hi) // 2
-        _, _, ina = _evaluate(mid, grid, d, d_idx, spec, ledger, cache, runner)
+        _, _, ina = yield mid
         if ina:
             hi = mid
         else:
             lo = mid
-    return (lo, hi), ledger
+    return lo, hi
+
+
+CALIBRATED_PROBES = 4     # probes placed by the calibrated surrogate before midpoints
+
+
+def match_index(ys, sim_log10, late) -> int:
+    """Grid index whose predicted curve is closest (mean |log10 rho| gap over
+    the late times) to a simulated curve."""
+    err = np.mean(np.abs(ys[:, late] - sim_log10[late]), axis=1)
+    return int(np.argmin(err))
+
+
+def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
+                    calibrated: int = CALIBRATED_PROBES):
+    """Bracket search whose probes the surrogate places. `ys` [grid, times]
+    are its log10 rho curves for the whole grid and `cls` their classes; its
+    flip f0 is the first grid point it predicts inactive inside the bracket.
+    Each simulated probe calibrates it: the grid index j whose predicted
+    curve best matches the simulated one over the last decade of t is where
+    the surrogate puts that curve, so its flip moves by (probe - j). The next
+    probe is the calibrated flip, or the point below it when the flip is
+    already the upper end of the bracket; when the estimate keeps pressing
+    against an end of the bracket the step from that end doubles. After
+    `calibrated` such probes, or after an extinct run (which calibrates
+    nothing), probes are midpoints. The simulation decides every class."""
+    ys = np.asarray(ys, float)
+    cls = np.asarray(cls, bool)
+    late = np.asarray(times, float) >= float(times[-1]) / 10.0
+    inside = np.nonzero(cls[lo + 1:hi + 1])[0]
+    f0 = lo + 1 + int(inside[0]) if inside.size else hi
+    shift, placed, streak, last_end = 0, 0, 0, None
+    while hi - lo > 1:
+        by_surrogate = placed < calibrated
+        if by_surrogate:
+            f = f0 + shift
+            end = "hi" if f >= hi else ("lo" if f <= lo + 1 else None)
+            streak = streak + 1 if (end is not None and end == last_end) else 0
+            last_end = end
+            step = 1 << streak
+            if end == "hi":
+                probe = max(hi - step, lo + 1)
+            elif end == "lo":
+                probe = min(lo + step, hi - 1)
+            else:
+                probe = f
+            placed += 1
+        else:
+            probe = (lo + hi) // 2
+        _, rho, ina = yield probe
+        if ina:
+            hi = probe
+        else:
+            lo = probe
+        if by_surrogate:
+            if rho[-1] > 0:
+                shift = probe - match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
+            else:
+                placed = calibrated  # extinct: no calibration, midpoints from here on
+    return lo, hi
+
+
+def drive(searches, spec: RunSpec, grid: Grid, runner=None):
+    """Run searches in lockstep. `searches` maps a name to (generator, d,
+    stream); every round simulates the pending probe of each unfinished
+    search in one batched run (`runner(spec, [(p, d, stream)])` ->
+    (times, [rho])). Returns {name: ((lo, hi), ledger)}."""
+    runner = runner or simulate_curves
+    state = {}
+    for name, (gen, d, st) in searches.items():
+        try:
+            state[name] = [gen, d, st, next(gen), Ledger(), {}, None]
+        except StopIteration as e:
+            state[name] = [None, d, st, None, Ledger(), {}, e.value]
+    while True:
+        live = [n for n, v in state.items() if v[0] is not None]
+        if not live:
+            break
+        todo = [n for n in live if state[n][3] not in state[n][5]]
+        if todo:
+            times, rhos = runner(spec, [(grid.p[state[n][3]], state[n][1], state[n][2]) for n in todo])
+            for n, rho in zip(todo, rhos):
+                i = state[n][3]
+                ina = classify(times, rho)
+                state[n][5][i] = (times, rho, ina)
+                _record(state[n][4], grid, i, times, rho, ina, spec)
+        for n in live:
+            v = state[n]
+            try:
+                v[3] = v[0].send(v[5][v[3]])
+            except StopIteration as e:
+                v[0], v[6] = None, e.value
+    return {n: (tuple(v[6]), v[4]) for n, v in state.items()}
+
+
+def _sequential(runner):
+    """Adapt a one-curve runner(spec, p, d, stream) to drive()."""
+    def run(spec, probes):
+        out = [runner(spec, p, d, st) for p, d, st in probes]
+        return out[0][0], [r for _, r in out]
+    return run
+
+
+def plain_bisect(d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
+                 lo: int = 0, hi: Optional[int] = None):
+    """Plain bisection alone; returns ((lo, hi), ledger)."""
+    hi = len(grid) - 1 if hi is None else hi
+    res = drive({"plain": (plain_steps(grid, lo, hi), d, d_idx)}, spec, grid,
+                _sequential(runner))
+    return res["plain"]
 
 
 def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
@@ -152,76 +268,17 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
     return y, np.array(cls, dtype=bool)
 
 
-CALIBRATED_PROBES = 4     # probes placed by the calibrated surrogate before midpoints
-
-
-def match_index(ys, sim_log10, late) -> int:
-    """Grid index whose predicted curve is closest (mean |log10 rho| gap over
-    the late times) to a simulated curve."""
-    err = np.mean(np.abs(ys[:, late] - sim_log10[late]), axis=1)
-    return int(np.argmin(err))
-
-
 def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
-                     lo: int = 0, hi: Optional[int] = None, cache=None, predictor=None,
+                     lo: int = 0, hi: Optional[int] = None, predictor=None,
                      calibrated: int = CALIBRATED_PROBES):
-    """Bracket search whose probes the surrogate places. The surrogate's curves
-    for the whole grid give its flip f0 (first grid point it predicts inactive
-    inside the bracket). Each simulated probe calibrates it: the grid index j
-    whose predicted curve best matches the simulated one over the last decade
-    of t is where the surrogate puts that curve, so its flip is moved by
-    (probe - j). The next probe is the calibrated flip, or the point below it
-    when the flip is already the upper end of the bracket; when the estimate
-    keeps pressing against an end of the bracket the step from that end
-    doubles. After `calibrated` such probes, or after an extinct run (which
-    calibrates nothing), probes are midpoints. The simulation decides every
-    class. `predictor(d, idx)` -> (log10 rho [len(idx), times], classes)
-    replaces the network (tests)."""
+    """The surrogate-guided search alone; `predictor(d, idx)` -> (log10 rho
+    [len(idx), times], classes) replaces the network (tests)."""
     hi = len(grid) - 1 if hi is None else hi
-    ledger = Ledger()
-    cache = {} if cache is None else cache
     predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
-    times = np.asarray(spec.times(), float)
-    late = times >= times[-1] / 10.0
     ys, cls = predictor(d, list(range(len(grid))))
-    ys = np.asarray(ys, float)
-    cls = np.asarray(cls, bool)
-    inside = np.nonzero(cls[lo + 1:hi + 1])[0]
-    f0 = lo + 1 + int(inside[0]) if inside.size else hi
-    shift, placed, streak, last_end = 0, 0, 0, None
-    while hi - lo > 1:
-        by_surrogate = placed < calibrated
-        if by_surrogate:
-            f = f0 + shift
-            if f >= hi:
-                end = "hi"
-            elif f <= lo + 1:
-                end = "lo"
-            else:
-                end = None
-            streak = streak + 1 if (end is not None and end == last_end) else 0
-            last_end = end
-            step = 1 << streak
-            if end == "hi":
-                probe = max(hi - step, lo + 1)
-            elif end == "lo":
-                probe = min(lo + step, hi - 1)
-            else:
-                probe = f
-            placed += 1
-        else:
-            probe = (lo + hi) // 2
-        _, rho, ina = _evaluate(probe, grid, d, d_idx, spec, ledger, cache, runner)
-        if ina:
-            hi = probe
-        else:
-            lo = probe
-        if by_surrogate:
-            if rho[-1] > 0:
-                shift = probe - match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
-            else:
-                placed = calibrated  # extinct: no calibration, midpoints from here on
-    return (lo, hi), ledger
+    gen = surrogate_steps(ys, cls, grid, spec.times(), lo, hi, calibrated)
+    res = drive({"surrogate": (gen, d, d_idx)}, spec, grid, _sequential(runner))
+    return res["surrogate"]
 
 
 # --------------------------------------------------------------------------
@@ -316,26 +373,39 @@ def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
                  "final_loss": loss}
 
 
-def search_pair(net, d, d_idx, spec: RunSpec, grid: Grid, log=print):
-    """Plain and surrogate-guided searches at one d, each with its own ledger
-    and cache (no run is shared between them)."""
+def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print, runner=None,
+                 predictor=None):
+    """Plain and surrogate-guided searches for every d, all driven in
+    lockstep (one batched GPU run per round), each with its own ledger and
+    cache: no run is shared between searches. Returns one record per d."""
     import time
 
-    t2 = time.perf_counter()
-    pb, pl = plain_bisect(d, d_idx, grid, spec, cache={})
-    t3 = time.perf_counter()
-    sb, sl = surrogate_bisect(net, d, d_idx, grid, spec, cache={})
-    t4 = time.perf_counter()
-    log(f"d={d}: plain {pb} in {pl.runs} runs, surrogate {sb} in {sl.runs} runs")
-    return {"d": d,
-            "plain": {"bracket": [float(grid.p[pb[0]]), float(grid.p[pb[1]])], "idx": list(pb),
-                      "runs": pl.runs, "site_updates": pl.site_updates, "s": t3 - t2,
-                      "path": pl.path},
-            "surrogate": {"bracket": [float(grid.p[sb[0]]), float(grid.p[sb[1]])],
-                          "idx": list(sb), "runs": sl.runs, "site_updates": sl.site_updates,
-                          "s": t4 - t3, "path": sl.path},
-            "same_bracket": pb == sb,
-            "gain": pl.site_updates / max(sl.site_updates, 1)}
+    predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
+    hi = len(grid) - 1
+    searches = {}
+    for d, k in zip(d_values, d_indices):
+        ys, cls = predictor(d, list(range(len(grid))))
+        searches[("plain", k)] = (plain_steps(grid, 0, hi), d, k)
+        searches[("surrogate", k)] = (surrogate_steps(ys, cls, grid, spec.times(), 0, hi), d, k)
+    t0 = time.perf_counter()
+    res = drive(searches, spec, grid, runner)
+    wall = time.perf_counter() - t0
+    out = []
+    for d, k in zip(d_values, d_indices):
+        pb, pl = res[("plain", k)]
+        sb, sl = res[("surrogate", k)]
+        log(f"d={d}: plain {pb} in {pl.runs} runs, surrogate {sb} in {sl.runs} runs")
+        out.append({"d": d,
+                    "plain": {"bracket": [float(grid.p[pb[0]]), float(grid.p[pb[1]])],
+                              "idx": list(pb), "runs": pl.runs, "site_updates": pl.site_updates,
+                              "path": pl.path},
+                    "surrogate": {"bracket": [float(grid.p[sb[0]]), float(grid.p[sb[1]])],
+                                  "idx": list(sb), "runs": sl.runs,
+                                  "site_updates": sl.site_updates, "path": sl.path},
+                    "same_bracket": pb == sb,
+                    "gain": pl.site_updates / max(sl.site_updates, 1),
+                    "wall_s_all_searches": wall})
+    return out
 
 
 def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int = 10,
@@ -352,8 +422,7 @@ def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int 
                     "p_range": [float(grid.p[0]), float(grid.p[-1])]},
            "training": training, "searches": []}
     try:
-        for d_idx, d in enumerate(d_values):
-            out["searches"].append(search_pair(net, d, d_idx, spec, grid, log))
+        out["searches"] = run_searches(net, d_values, range(len(d_values)), spec, grid, log)
     finally:
         net.close()
     return out
@@ -400,10 +469,8 @@ def main(argv=None):
         np.save(a.save_net, net.params())
     if not a.train_only:
         keep = range(len(d_values)) if a.d_index is None else [int(v) for v in a.d_index.split(",")]
-        for k in keep:
-            r = search_pair(net, d_values[k], k, spec, grid, log)
-            res["searches"].append(r)
-            print(json.dumps({"search": r}), flush=True)
+        res["searches"] = run_searches(net, [d_values[k] for k in keep], list(keep), spec, grid,
+                                       log)
     net.close()
     print(json.dumps(res), flush=True)
 

@@ -77,6 +77,15 @@ def test_small_rings_and_block_widths(pcpd, L, B, model):
     _compare_full(pcpd, model, B, 2, 1, insts, [1, 2, 17])
 
 
+@pytest.mark.parametrize("L,B,model", [(32 * 700, 32, 2), (96 * 150, 96, 2), (16 * 1500, 16, 3),
+                                       (64 * 700, 64, 1)])
+def test_block_widths_over_many_tiles(pcpd, L, B, model):
+    """Other block widths than 64 take the general tile copies (and, above
+    64, tiles larger than the register prefetch); many tiles per ring."""
+    insts = [Instance(0.15, 0.4, L, 5), Instance(0.1, 0.7, L + 2 * B, 6)]
+    _compare_full(pcpd, model, B, 2, 4, insts, [3, 10])
+
+
 def test_host_init_resume_and_chunking(pcpd):
     L = 64 * 40
     start = wl.random_lattice(L, 2, 0.4, 21)

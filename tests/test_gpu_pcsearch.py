@@ -1,0 +1,112 @@
+"""The p_c search on the GPU at small scale: the curves it classifies are the
+oracle's, the training rows are the oracle's, an exact predictor closes the
+bracket in at most two verification runs, and the end-to-end comparison
+returns verified brackets with consistent site-update ledgers."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle
+from paper_1301_6082_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1301_6082_amd import pcsearch
+    return pcsearch
+
+
+def _oracle_rho(spec, insts, seed, planes):
+    times = spec.times()
+    runs = [oracle.Run(model="pcpd", B=spec.B, L=i.L, seed=seed, stream=i.stream_id, plane=q,
+                       p=i.p, d=i.d, times=times)
+            for i in insts for q in range(planes)]
+    oracle.simulate_many(runs)
+    out = []
+    for k, inst in enumerate(insts):
+        n = sum(runs[k * planes + q].counts()[0] for q in range(planes))
+        out.append(np.asarray(n, np.float64) / (64.0 * planes * inst.L))
+    return np.asarray(times, float), out
+
+
+def test_simulated_curve_is_the_oracle_curve(ps):
+    spec = ps.RunSpec(L=1024, planes=2, steps=300, records=16)
+    t, rho = ps.simulate_curve(spec, 0.12, 0.5, stream=1)
+    ot, orho = _oracle_rho(spec, [workloads.Instance(0.12, 0.5, 1024, 1)], ps.SEED, 2)
+    np.testing.assert_array_equal(t, ot)
+    np.testing.assert_array_equal(rho, orho[0])
+
+
+def test_batched_probes_equal_single_runs(ps):
+    spec = ps.RunSpec(L=2048, planes=2, steps=400, records=16)
+    probes = [(0.11, 0.1, 0), (0.16, 0.5, 1), (0.11, 0.1, 0), (0.23, 0.9, 2)]
+    t, rhos = ps.simulate_curves(spec, probes)
+    for (p, d, st), rho in zip(probes, rhos):
+        t1, r1 = ps.simulate_curve(spec, p, d, st)
+        np.testing.assert_array_equal(t, t1)
+        np.testing.assert_array_equal(rho, r1)
+    np.testing.assert_array_equal(rhos[0], rhos[2])
+
+
+def test_training_rows_are_the_oracle_rows(ps):
+    spec = ps.RunSpec(steps=200, records=12)
+    insts = ps.training_batch(6, spec, seed=5, L_range=(1024, 4096))
+    x, y, m, su = ps.simulate_training_set(insts, spec, seed=5)
+    times, orho = _oracle_rho(spec, insts, 5, 1)
+    rho = np.stack(orho, axis=1).ravel()                      # [times, inst] order
+    assert su == sum(64 * i.L for i in insts) * spec.steps
+    np.testing.assert_array_equal(m, (rho > 0).astype(np.float32))
+    live = rho > 0
+    np.testing.assert_allclose(y[live], np.log10(rho[live]).astype(np.float32), rtol=0, atol=1e-6)
+    P = np.repeat(np.array([[i.p for i in insts]]), len(times), 0).ravel()
+    np.testing.assert_allclose(x[:, 0], P / 0.25, rtol=1e-6)
+
+
+def _valid_bracket(br, cls, n):
+    lo, hi = br
+    assert hi - lo == 1
+    assert lo == 0 or not cls[lo]
+    assert hi == n - 1 or cls[hi]
+
+
+def test_exact_predictor_closes_the_bracket_in_two_runs(ps):
+    spec = ps.RunSpec(L=4096, planes=1, steps=2000, records=32)
+    grid = ps.Grid(bits=5)
+    d, d_idx = 0.5, 1
+    curves = {i: ps.simulate_curve(spec, grid.p[i], d, d_idx) for i in range(len(grid))}
+    cls = np.array([ps.classify(*curves[i]) for i in range(len(grid))])
+    print(f"[pcsearch] classes {''.join('I' if c else 'a' for c in cls)}", flush=True)
+
+    def predictor(dd, idx):
+        ys = np.stack([np.log10(np.maximum(curves[i][1], 1e-300)) for i in idx])
+        return ys, cls[np.asarray(idx)]
+
+    pb, pl = ps.plain_bisect(d, d_idx, grid, spec)
+    sb, sl = ps.surrogate_bisect(None, d, d_idx, grid, spec, predictor=predictor)
+    _valid_bracket(pb, cls, len(grid))
+    _valid_bracket(sb, cls, len(grid))
+    assert sl.runs <= 2
+    assert pl.runs == 5 and pl.site_updates == 5 * spec.site_updates()
+    first = int(np.argmax(cls)) if cls.any() else len(grid) - 1
+    monotone = cls.any() and cls[first:].all()
+    if monotone:
+        assert pb == sb == (first - 1, first)
+
+
+def test_compare_end_to_end_small(ps):
+    spec = ps.RunSpec(L=2048, planes=1, steps=1000, records=24)
+    res = ps.compare(d_values=(0.5,), spec=spec, bits=5, train_count=48, train_batches=1,
+                     train_L=(1024, 4096), epochs=20, log=lambda s: None)
+    tr = res["training"]
+    assert tr["curves"] == 48 and tr["rows"] == 48 * 24 and np.isfinite(tr["final_loss"])
+    (s,) = res["searches"]
+    for side in ("plain", "surrogate"):
+        lo, hi = s[side]["idx"]
+        assert hi - lo == 1
+        assert s[side]["site_updates"] == s[side]["runs"] * spec.site_updates()
+    assert s["plain"]["runs"] == 5
+    assert 1 <= s["surrogate"]["runs"] <= 31

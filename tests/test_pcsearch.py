@@ -54,7 +54,7 @@ def _fake_runner(flip):
     """Class of grid point i: inactive iff i >= flip; the curve encodes it."""
     grid = ps.Grid(bits=10)
 
-    def run(spec, p, d, seed, stream):
+    def run(spec, p, d, stream):
         i = int(np.argmin(np.abs(grid.p - p)))
         return TIMES, curve("inactive" if i >= flip else "active")
     return run
@@ -125,7 +125,7 @@ def family(i, F):
 def _family_runner(F):
     grid = ps.Grid(bits=10)
 
-    def run(spec, p, d, seed, stream):
+    def run(spec, p, d, stream):
         i = int(np.argmin(np.abs(grid.p - p)))
         return TIMES, family(i, F)
     return run
@@ -180,3 +180,37 @@ def test_match_index_finds_the_nearest_curve():
 def test_features():
     x = ps.features([0.25, 0.125], [0.5, 0.1], [1.0, 1e6])
     np.testing.assert_allclose(x, [[1.0, 0.5, 0.0], [0.5, 0.1, 1.0]], rtol=1e-6)
+
+
+def test_lockstep_searches_match_the_sequential_ones():
+    """drive() runs all searches in batched rounds; each search's bracket,
+    runs and path equal those of running it alone, and every round batches
+    the pending probes of all unfinished searches."""
+    grid = ps.Grid(bits=10)
+    flips = {0: 333, 1: 480, 2: 701}
+    batches = []
+
+    def runner(spec, probes):
+        batches.append(len(probes))
+        out = []
+        for p, d, stream in probes:
+            i = int(np.argmin(np.abs(grid.p - p)))
+            out.append(family(i, flips[stream]))
+        return TIMES, out
+
+    def predictor_for(F):
+        return _family_predictor(F)
+
+    res = ps.run_searches(None, [0.1, 0.5, 0.9], [0, 1, 2], SPEC, grid, log=lambda s: None,
+                          runner=runner,
+                          predictor=lambda d, idx: predictor_for({0.1: 340, 0.5: 470, 0.9: 701}[d])(d, idx))
+    assert max(batches) == 6 and len(batches) == 10
+    for rec, k in zip(res, (0, 1, 2)):
+        F = flips[k]
+        assert rec["plain"]["idx"] == [F - 1, F] == rec["surrogate"]["idx"]
+        assert rec["plain"]["runs"] == 10 and rec["surrogate"]["runs"] <= 3
+        alone, led = ps.surrogate_bisect(None, rec["d"], k, grid, SPEC,
+                                         runner=_family_runner(F),
+                                         predictor=predictor_for({0: 340, 1: 470, 2: 701}[k]))
+        assert list(alone) == rec["surrogate"]["idx"] and led.runs == rec["surrogate"]["runs"]
+        assert [e[0] for e in led.path] == [e[0] for e in rec["surrogate"]["path"]]
