@@ -154,11 +154,12 @@ PCPD_API int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning);
 
 /* Options of a context (bit flags). */
 typedef enum {
-    PCPD_OPT_GRAPH = 1  /* capture each pcpd_sweep / pcpd_run batch into a HIP graph on first
-                           use and replay it when the same batch (same Monte Carlo step
-                           increments and record slots, same copy parity) comes again; the
-                           kernels read the substep index from a device clock, so a replay is
-                           valid at any starting time. Ignored while profiling. */
+    PCPD_OPT_GRAPH = 1  /* run the sweeps of pcpd_sweep / pcpd_run in segments of a fixed
+                           number of Monte Carlo steps (256 phase launches), each captured into
+                           a HIP graph on first use and replayed whenever a segment comes again
+                           (same copy parity); the kernels read the substep index from a device
+                           clock, so a replay is valid at any starting time. Remainders and
+                           density records are launched directly. Ignored while profiling. */
 } pcpd_option;
 
 PCPD_API int pcpd_set_options(pcpd_ctx *ctx, uint32_t options);

@@ -314,29 +314,54 @@ hipError_t capture_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops,
     return hipSuccess;
 }
 
-// Run a batch: replay a cached graph of the same batch, capture one, or
-// launch directly (profiling on, or graphs off).
+// Phase launches per captured graph. A run of 10^6 Monte Carlo steps is
+// 10^5..10^6 launches; one graph of them all exhausts the runtime, so long
+// batches are cut into segments of a fixed number of steps, each replayed
+// from one cached graph.
+constexpr uint64_t kLaunchesPerGraph = 256;
+
+// Run a batch. With graphs on (and not profiling), every whole segment of
+// `seg` steps without a record replays the cached graph of that segment
+// (captured on first use), and the rest of each op (fewer steps, and its
+// density record) is launched directly; otherwise everything is launched
+// directly.
 hipError_t execute_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops) {
-    int cur = ctx->cur;
-    uint64_t steps = 0;
-    for (const BatchOp &op : ops) steps += op.steps;
-    if ((ctx->options & PCPD_OPT_GRAPH) && !ctx->profiling) {
-        pcpd_ctx::GraphEntry *g = nullptr;
-        for (auto *c : ctx->graphs)
-            if (c->cur_in == ctx->cur && c->ops == ops) g = c;
-        if (!g) {
-            hipError_t e = capture_ops(ctx, ops, &g);
-            if (e != hipSuccess) return e;
-        }
-        hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
-        if (e != hipSuccess) return e;
-        cur = g->cur_out;
-    } else {
+    if (!(ctx->options & PCPD_OPT_GRAPH) || ctx->profiling) {
+        int cur = ctx->cur;
+        uint64_t steps = 0;
+        for (const BatchOp &op : ops) steps += op.steps;
         hipError_t e = enqueue_ops(ctx, ops, ctx->stream, ctx->profiling, &cur);
         if (e != hipSuccess) return e;
+        ctx->cur = cur;
+        ctx->t += steps;
+        return hipSuccess;
     }
-    ctx->cur = cur;
-    ctx->t += steps;
+    const uint64_t seg = std::max<uint64_t>(1, kLaunchesPerGraph * ctx->phase_max / ctx->B);
+    for (const BatchOp &op : ops) {
+        uint64_t left = op.steps;
+        while (left >= seg) {
+            const std::vector<BatchOp> one{BatchOp{seg, -1}};
+            pcpd_ctx::GraphEntry *g = nullptr;
+            for (auto *c : ctx->graphs)
+                if (c->cur_in == ctx->cur && c->ops == one) g = c;
+            if (!g) {
+                hipError_t e = capture_ops(ctx, one, &g);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
+            if (e != hipSuccess) return e;
+            ctx->cur = g->cur_out;
+            ctx->t += seg;
+            left -= seg;
+        }
+        if (left || op.slot >= 0) {
+            int cur = ctx->cur;
+            hipError_t e = enqueue_ops(ctx, {BatchOp{left, op.slot}}, ctx->stream, false, &cur);
+            if (e != hipSuccess) return e;
+            ctx->cur = cur;
+            ctx->t += left;
+        }
+    }
     return hipSuccess;
 }
 

@@ -77,6 +77,7 @@ class RunSpec:
     records: int = 64
     B: int = 64
     model: int = workloads.PCPD
+    tune: bool = True   # autotune the kernel shape of each batched verification run
 
     def times(self):
         return workloads.log_times(self.steps, self.records)
@@ -97,6 +98,9 @@ def simulate_curves(spec: RunSpec, probes: Sequence[Tuple[float, float, int]]):
     insts = [workloads.Instance(float(p), float(d), spec.L, int(st)) for p, d, st in probes]
     times = spec.times()
     with pcpd.Sim(spec.model, spec.B, spec.planes, SEED, insts) as sim:
+        if spec.tune:
+            sim.autotune(2)   # cached per lattice shape; never changes results
+        sim.set_options(graph=True)
         c = sim.run(times)
     N = c[:, :, :, 0].astype(np.float64).sum(axis=2)           # [times, instance]
     rho = N / (64.0 * spec.planes * spec.L)
@@ -205,13 +209,14 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
     return lo, hi
 
 
-def drive(searches, spec: RunSpec, grid: Grid, runner=None):
+def drive(searches, spec: RunSpec, grid: Grid, runner=None, log=None):
     """Run searches in lockstep. `searches` maps a name to (generator, d,
     stream); every round simulates the pending probe of each unfinished
     search in one batched run (`runner(spec, [(p, d, stream)])` ->
     (times, [rho])). Returns {name: ((lo, hi), ledger)}."""
     runner = runner or simulate_curves
     state = {}
+    rounds = 0
     for name, (gen, d, st) in searches.items():
         try:
             state[name] = [gen, d, st, next(gen), Ledger(), {}, None]
@@ -224,6 +229,10 @@ def drive(searches, spec: RunSpec, grid: Grid, runner=None):
         todo = [n for n in live if state[n][3] not in state[n][5]]
         if todo:
             times, rhos = runner(spec, [(grid.p[state[n][3]], state[n][1], state[n][2]) for n in todo])
+            rounds += 1
+            if log:
+                log(f"round {rounds}: simulated {len(todo)} probes "
+                    f"{[(str(n), int(state[n][3])) for n in todo]}")
             for n, rho in zip(todo, rhos):
                 i = state[n][3]
                 ina = classify(times, rho)
@@ -347,7 +356,7 @@ def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-
 
 def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
                     train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
-                    epochs: int = 150, seed: int = 2013, log=print):
+                    epochs: int = 150, seed: int = 2013, log=print, p_range=(0.04, 0.30)):
     """Simulate the training curves (batched runs at the search's horizon) and
     train a surrogate on them. Returns (net, training summary)."""
     import time
@@ -358,10 +367,13 @@ def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
     t0 = time.perf_counter()
     xs, ys, ms, train_su = [], [], [], 0
     for b in range(train_batches):
-        insts = training_batch(train_count, spec, seed + b, d_values=d_values, L_range=train_L)
+        insts = training_batch(train_count, spec, seed + b, d_values=d_values, L_range=train_L,
+                               p_range=p_range)
         x, y, m, su = simulate_training_set(insts, spec, seed + b)
         xs.append(x), ys.append(y), ms.append(m)
         train_su += su
+        log(f"training batch {b + 1}/{train_batches}: {len(insts)} curves, "
+            f"{time.perf_counter() - t0:.1f} s")
     x, y, m = np.concatenate(xs), np.concatenate(ys), np.concatenate(ms)
     t_data = time.perf_counter() - t0
     net = pcpd.Surrogate(seed=seed)
@@ -388,7 +400,7 @@ def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print,
         searches[("plain", k)] = (plain_steps(grid, 0, hi), d, k)
         searches[("surrogate", k)] = (surrogate_steps(ys, cls, grid, spec.times(), 0, hi), d, k)
     t0 = time.perf_counter()
-    res = drive(searches, spec, grid, runner)
+    res = drive(searches, spec, grid, runner, log)
     wall = time.perf_counter() - t0
     out = []
     for d, k in zip(d_values, d_indices):
@@ -447,6 +459,7 @@ def main(argv=None):
     ap.add_argument("--save-net", type=str, default=None, help="write trained parameters (.npy)")
     ap.add_argument("--load-net", type=str, default=None, help="read parameters, skip training")
     ap.add_argument("--train-only", action="store_true")
+    ap.add_argument("--train-p", type=str, default="0.04,0.30", help="p range of the training curves")
     a = ap.parse_args(argv)
     from . import pcpd
 
@@ -463,7 +476,8 @@ def main(argv=None):
     else:
         net, res["training"] = build_surrogate(
             d_values, spec, a.train_count, a.train_batches,
-            tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log)
+            tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log,
+            p_range=tuple(float(v) for v in a.train_p.split(",")))
         print(json.dumps({"training": res["training"]}), flush=True)
     if a.save_net:
         np.save(a.save_net, net.params())

@@ -237,14 +237,18 @@ def test_profiling_does_not_change_results(pcpd):
 
 
 def test_graph_replays_match_direct_launches(pcpd):
-    """PCPD_OPT_GRAPH: batches are captured once and replayed; every replay,
-    with eager work between replays, must equal direct launches."""
+    """PCPD_OPT_GRAPH: segments of a fixed number of steps are captured once
+    and replayed (phases of 4 substeps: 16 steps per segment, so every run
+    below replays segments and launches remainders and records directly);
+    every replay, with eager work between replays, must equal direct
+    launches."""
     insts = [Instance(0.1, 0.3, 64 * 200, 0), Instance(0.22, 0.6, 64 * 37, 1)]
     with pcpd.Sim(2, 64, 2, 4, insts) as g, pcpd.Sim(2, 64, 2, 4, insts) as d:
+        g.set_tuning(128, 4)
         g.set_options(graph=True)
         for rep in range(4):
             t = g.time
-            sched = [t + 2, t + 4, t + 8]
+            sched = [t + 20, t + 40, t + 75]
             cg, cd = g.run(sched), d.run(sched)
             np.testing.assert_array_equal(cg, cd, err_msg=f"replay {rep}")
             for i in range(2):
@@ -283,11 +287,12 @@ def test_batch_in_one_graph_launch_matches_instances_alone(pcpd):
     run give the same lattices as each instance in a context of its own."""
     c = wl.cfg3(count=24)
     with pcpd.Sim(c.model, c.B, 1, c.seed, c.instances) as sim:
+        sim.set_tuning(128, 4)   # 16-step graph segments
         sim.set_options(graph=True)
-        batch = sim.run([5, 10])
+        batch = sim.run([5, 40])
         lat = [sim.get_lattice(i) for i in range(len(c.instances))]
     for i in (0, 5, 17, 23):
         with pcpd.Sim(c.model, c.B, 1, c.seed, [c.instances[i]]) as alone:
-            a = alone.run([5, 10])
+            a = alone.run([5, 40])
             np.testing.assert_array_equal(alone.get_lattice(0), lat[i], err_msg=f"inst {i}")
             np.testing.assert_array_equal(a[:, 0], batch[:, i])
