@@ -164,21 +164,30 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
                     calibrated: int = CALIBRATED_PROBES):
     """Bracket search whose probes the surrogate places. `ys` [grid, times]
     are its log10 rho curves for the whole grid and `cls` their classes; its
-    flip f0 is the first grid point it predicts inactive inside the bracket.
+    flip f0 is where its last run of inactive predictions inside the bracket
+    starts.
     Each simulated probe calibrates it: the grid index j whose predicted
     curve best matches the simulated one over the last decade of t is where
     the surrogate puts that curve, so its flip moves by (probe - j). The next
     probe is the calibrated flip, or the point below it when the flip is
     already the upper end of the bracket; when the estimate keeps pressing
-    against an end of the bracket the step from that end doubles. After
-    `calibrated` such probes, or after an extinct run (which calibrates
-    nothing), probes are midpoints. The simulation decides every class."""
+    against an end of the bracket the step from that end doubles. Once both
+    ends of the bracket come from simulations, an interior proposal outside
+    the middle half of the bracket, or a repeated press against an end, is
+    replaced by the midpoint. After `calibrated` such
+    probes, or after an extinct run (which calibrates nothing), probes are
+    midpoints. The simulation decides every class."""
     ys = np.asarray(ys, float)
     cls = np.asarray(cls, bool)
     late = np.asarray(times, float) >= float(times[-1]) / 10.0
-    inside = np.nonzero(cls[lo + 1:hi + 1])[0]
-    f0 = lo + 1 + int(inside[0]) if inside.size else hi
+    # the surrogate's flip: the start of its last run of inactive predictions
+    # inside the bracket (spurious inactive predictions far below it, e.g.
+    # where the network extrapolates, do not count)
+    active_pred = np.nonzero(~cls[lo + 1:hi + 1])[0]
+    f0 = lo + 2 + int(active_pred[-1]) if active_pred.size else lo + 1
+    f0 = min(f0, hi)
     shift, placed, streak, last_end = 0, 0, 0, None
+    lo_seen = hi_seen = False  # ends of the bracket established by simulation
     while hi - lo > 1:
         by_surrogate = placed < calibrated
         if by_surrogate:
@@ -193,14 +202,22 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
                 probe = min(lo + step, hi - 1)
             else:
                 probe = f
+            if lo_seen and hi_seen:
+                # both ends simulated: an interior proposal outside the middle
+                # half of the bracket, or a repeated press against one end, is
+                # replaced by the midpoint; a first press (the point next to an
+                # end, which closes the bracket if the surrogate is right) stays
+                q = (hi - lo) // 4
+                if (end is None and not (lo + q <= probe <= hi - q)) or streak > 0:
+                    probe = (lo + hi) // 2
             placed += 1
         else:
             probe = (lo + hi) // 2
         _, rho, ina = yield probe
         if ina:
-            hi = probe
+            hi, hi_seen = probe, True
         else:
-            lo = probe
+            lo, lo_seen = probe, True
         if by_surrogate:
             if rho[-1] > 0:
                 shift = probe - match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
@@ -460,6 +477,8 @@ def main(argv=None):
     ap.add_argument("--load-net", type=str, default=None, help="read parameters, skip training")
     ap.add_argument("--train-only", action="store_true")
     ap.add_argument("--train-p", type=str, default="0.04,0.30", help="p range of the training curves")
+    ap.add_argument("--train-d", type=str, default=None,
+                    help="d values of the training curves (default: the searched --d)")
     a = ap.parse_args(argv)
     from . import pcpd
 
@@ -474,8 +493,9 @@ def main(argv=None):
         net = pcpd.Surrogate(seed=0)
         net.set_params(np.load(a.load_net))
     else:
+        train_d = d_values if a.train_d is None else tuple(float(v) for v in a.train_d.split(","))
         net, res["training"] = build_surrogate(
-            d_values, spec, a.train_count, a.train_batches,
+            train_d, spec, a.train_count, a.train_batches,
             tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log,
             p_range=tuple(float(v) for v in a.train_p.split(",")))
         print(json.dumps({"training": res["training"]}), flush=True)

@@ -214,3 +214,35 @@ def test_lockstep_searches_match_the_sequential_ones():
                                          predictor=predictor_for({0: 340, 1: 470, 2: 701}[k]))
         assert list(alone) == rec["surrogate"]["idx"] and led.runs == rec["surrogate"]["runs"]
         assert [e[0] for e in led.path] == [e[0] for e in rec["surrogate"]["path"]]
+
+
+def test_spurious_low_predictions_do_not_move_the_flip():
+    """A network that also predicts 'inactive' at the lowest p (where it
+    extrapolates) still proposes its real flip first."""
+    grid = ps.Grid(bits=10)
+    F = 780
+
+    def pred(d, idx):
+        ys, cls = _family_predictor(F)(d, idx)
+        cls = cls.copy()
+        cls[:20] = True
+        return ys, cls
+    (lo, hi), led = ps.surrogate_bisect(None, 0.9, 2, grid, SPEC, runner=_family_runner(F),
+                                        predictor=pred)
+    assert (lo, hi) == (F - 1, F)
+    assert led.path[0][0] == F and led.runs <= 2
+
+
+def test_two_sided_proposals_stay_in_the_middle_half():
+    """Once both ends are simulated, proposals near an end of the bracket are
+    replaced by midpoints, so a badly calibrated surrogate costs at most a
+    few runs more than bisection."""
+    grid = ps.Grid(bits=10)
+    rng = np.random.default_rng(7)
+    for F in (100, 333, 700, 1000):
+        def garbage(d, idx):
+            return rng.normal(size=(len(idx), TIMES.size)), rng.random(len(idx)) < 0.5
+        (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_family_runner(F),
+                                            predictor=garbage)
+        assert (lo, hi) == (F - 1, F)
+        assert led.runs <= ps.CALIBRATED_PROBES + 10
