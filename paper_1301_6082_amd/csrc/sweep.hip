@@ -161,9 +161,12 @@ __device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t 
 // of either kind, and the short, latency-bound update path overlaps the
 // arithmetic of the draws. Each wavefront draws the local sites of 64
 // substeps at a time, one per lane, and reads them back with v_readlane.
-// Lanes whose window would leave the loaded columns (block 0 when o == 0,
-// the last block when o+N >= B, lanes past the tile) work on the spare
-// columns trash-1 .. trash+1 instead, so no branch depends on the lane.
+// Window rows o-1 .. o+N lie inside the lane's own column when
+// 1 <= o <= B-1-N; otherwise (a uniform branch, (N+1)/B of the substeps) the
+// window spills into a neighbouring column and each word has its own
+// address. Lanes whose window would leave the loaded columns (block 0 when
+// o == 0, the last block when o+N >= B, lanes past the tile) work on the
+// spare columns trash-1 .. trash+1 instead, so no branch depends on the lane.
 template <int N, int KDH, int KPH>
 __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, uint32_t kg,
                                              uint32_t c, uint32_t team, uint32_t ncols,
@@ -172,6 +175,7 @@ __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, u
     const uint32_t lane = __lane_id();
     const bool active = c < ncols;
     const bool first = c == 0u, last = c + 1u == ncols;
+    const uint32_t col_in = active ? c : trash;  // column of a window inside one column
     Masks cur{};
     if (team == 0u) cur = window_masks<KDH, KPH>(ld, kg, s0);
     for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
@@ -181,25 +185,43 @@ __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, u
             const uint32_t it = it0 + j;
             if ((it & 1u) == team) {
                 const uint32_t o = __builtin_amdgcn_readlane(sites, j);
-                // window sites o-1 .. o+N of block c; they spill into block
-                // c-1 when o == 0 and into block c+1 when o+N >= B
-                const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
-                const int col = static_cast<int>(ok ? c : trash);
-                int base[N + 2];
-                window_offsets<N>(o, B, ldw, base);
                 uint32_t wl[N + 2], wh[N + 2];
+                if (o - 1u < B - 1u - N) {
+                    // window rows o-1 .. o+N inside the lane's own column: one
+                    // address plus multiples of the pitch (all but (N+1)/B of
+                    // the substeps)
+                    uint64_t *w = lds + ((o - 1u) * ldw + col_in);
 #pragma unroll
-                for (int m = 0; m < N + 2; ++m) {
-                    const uint64_t v = lds[base[m] + col];
-                    wl[m] = static_cast<uint32_t>(v);
-                    wh[m] = static_cast<uint32_t>(v >> 32);
+                    for (int m = 0; m < N + 2; ++m) {
+                        const uint64_t v = w[m * ldw];
+                        wl[m] = static_cast<uint32_t>(v);
+                        wh[m] = static_cast<uint32_t>(v >> 32);
+                    }
+                    attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
+                    attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
+#pragma unroll
+                    for (int m = 0; m < N + 2; ++m)
+                        w[m * ldw] = static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
+                } else {
+                    // window sites o-1 .. o+N of block c spill into block c-1
+                    // when o == 0 and into block c+1 when o+N >= B
+                    const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
+                    const int col = static_cast<int>(ok ? c : trash);
+                    int base[N + 2];
+                    window_offsets<N>(o, B, ldw, base);
+#pragma unroll
+                    for (int m = 0; m < N + 2; ++m) {
+                        const uint64_t v = lds[base[m] + col];
+                        wl[m] = static_cast<uint32_t>(v);
+                        wh[m] = static_cast<uint32_t>(v >> 32);
+                    }
+                    attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
+                    attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
+#pragma unroll
+                    for (int m = 0; m < N + 2; ++m)
+                        lds[base[m] + col] =
+                            static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
                 }
-                attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
-                attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
-#pragma unroll
-                for (int m = 0; m < N + 2; ++m)
-                    lds[base[m] + col] =
-                        static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
             } else if (it + 1u < S) {
                 cur = window_masks<KDH, KPH>(ld, kg, s0 + it + 1u);
             }
