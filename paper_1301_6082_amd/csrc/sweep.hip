@@ -248,6 +248,11 @@ __device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
 // flight hide the memory latency.
 constexpr int kCopyBatch = 16;
 
+// Two consecutive sites of one block, moved as one 16-byte access.
+struct alignas(16) WordPair {
+    uint64_t a, b;
+};
+
 // Copy `total` words of a tile, ring blocks kfirst, kfirst+1, ... (mod nb),
 // from HBM (natural order) into LDS column-per-block. Lane i handles words
 // i, i+nthr, ...; (column, row, ring block) advance incrementally.
@@ -280,6 +285,45 @@ __device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restr
     }
 }
 
+// load_tile for an even B and a 16-byte aligned ring: lane i handles the
+// site pairs (2i, 2i+1), (2i+2*nthr, ...), ..., so a tile of up to
+// 2*kCopyBatch*nthr words arrives in one round trip.
+__device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *__restrict__ ring,
+                                                uint32_t kfirst, uint32_t nb, uint32_t total,
+                                                uint32_t B, uint32_t ldw, uint32_t tid,
+                                                uint32_t nthr) {
+    const WordPair *rp = reinterpret_cast<const WordPair *>(ring);
+    const uint32_t step = 2u * nthr;
+    const uint32_t cstep = step / B, ostep = step - cstep * B, kstep = cstep % nb;
+    uint32_t c = (2u * tid) / B, o = 2u * tid - c * B;
+    uint32_t kg = (kfirst + c) % nb;
+    const uint32_t half = B >> 1;
+    for (uint32_t i0 = 2u * tid; i0 < total; i0 += kCopyBatch * step) {
+        WordPair v[kCopyBatch];
+        uint32_t a[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            a[u] = o * ldw + c;
+            if (i0 + u * step < total) v[u] = rp[static_cast<uint64_t>(kg) * half + (o >> 1)];
+            c += cstep;
+            o += ostep;
+            kg += kstep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+                ++kg;
+            }
+            if (kg >= nb) kg -= nb;
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * step < total) {
+                lds[a[u]] = v[u].a;
+                lds[a[u] + ldw] = v[u].b;
+            }
+    }
+}
+
 // Copy the interior columns hb .. hb+total/B-1 of the tile back to HBM, where
 // they are `total` consecutive words starting at `out`.
 __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const uint64_t *lds,
@@ -302,6 +346,37 @@ __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const
 #pragma unroll
         for (int u = 0; u < kCopyBatch; ++u)
             if (i0 + u * nthr < total) out[i0 + u * nthr] = v[u];
+    }
+}
+
+// store_interior for an even B and a 16-byte aligned destination, one site
+// pair per lane and access.
+__device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
+                                                     const uint64_t *lds, uint32_t hb,
+                                                     uint32_t total, uint32_t B, uint32_t ldw,
+                                                     uint32_t tid, uint32_t nthr) {
+    WordPair *op = reinterpret_cast<WordPair *>(out);
+    const uint32_t step = 2u * nthr;
+    const uint32_t cstep = step / B, ostep = step - cstep * B;
+    uint32_t c = (2u * tid) / B, o = 2u * tid - c * B;
+    for (uint32_t i0 = 2u * tid; i0 < total; i0 += kCopyBatch * step) {
+        WordPair v[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            if (i0 + u * step < total) {
+                v[u].a = lds[o * ldw + hb + c];
+                v[u].b = lds[(o + 1u) * ldw + hb + c];
+            }
+            c += cstep;
+            o += ostep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * step < total) op[(i0 + u * step) >> 1] = v[u];
     }
 }
 
@@ -329,14 +404,23 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         (static_cast<uint64_t>(td.k0) + static_cast<uint64_t>(nb) * ((hb + nb - 1u) / nb) - hb) %
         nb);
 
+    // even B and 16-byte aligned buffers: tile copies move site pairs
+    const bool pairs = (B & 1u) == 0u &&
+                       ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0u;
+
     // ---- load tile + halo: consecutive lanes read consecutive words
-    load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    if (pairs)
+        load_tile_pairs(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    else
+        load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     __syncthreads();
 
     // ---- S substeps in LDS, one window (block) per lane
     {
+        // half is a multiple of the wavefront size, so the team is uniform
+        // per wavefront and its branches stay on the scalar unit
         const uint32_t half = nthr >> 1;
-        const uint32_t team = tid >= half ? 1u : 0u;
+        const uint32_t team = __builtin_amdgcn_readfirstlane(tid >= half ? 1u : 0u);
         const uint32_t c = tid - team * half;
         const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
         uint32_t kg = kfirst + c;
@@ -351,8 +435,11 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     }
 
     // ---- write the interior back; it is contiguous in the ring
-    store_interior(dst + ld.base + static_cast<uint64_t>(td.k0) * B, lds, hb, td.kint * B, B, ldw,
-                   tid, nthr);
+    uint64_t *out = dst + ld.base + static_cast<uint64_t>(td.k0) * B;
+    if (pairs)
+        store_interior_pairs(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+    else
+        store_interior(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
 }
 
 __global__ void fill_words(uint64_t *__restrict__ dst, uint64_t n, uint64_t value) {

@@ -78,10 +78,10 @@ def test_small_rings_and_block_widths(pcpd, L, B, model):
 
 
 @pytest.mark.parametrize("L,B,model", [(32 * 700, 32, 2), (96 * 150, 96, 2), (16 * 1500, 16, 3),
-                                       (64 * 700, 64, 1)])
+                                       (64 * 700, 64, 1), (15 * 1400, 15, 2), (9 * 2000, 9, 3)])
 def test_block_widths_over_many_tiles(pcpd, L, B, model):
-    """Other block widths than 64 take the general tile copies (and, above
-    64, tiles larger than the register prefetch); many tiles per ring."""
+    """Block widths other than 64 over many tiles per ring: even widths move
+    tiles as 16-byte site pairs, odd widths one word at a time."""
     insts = [Instance(0.15, 0.4, L, 5), Instance(0.1, 0.7, L + 2 * B, 6)]
     _compare_full(pcpd, model, B, 2, 4, insts, [3, 10])
 
