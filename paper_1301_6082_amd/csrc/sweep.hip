@@ -75,13 +75,17 @@ struct Masks {
     W2 D, Am, R;
 };
 
-// The three draws of one window advanced round by round together: six
-// independent 32x32->64 products per round keep the VALU pipeline full even
-// with one wavefront per SIMD. Round 1 is identical for the three draws
-// (they differ only in counter word 1) and is computed once by the compiler.
-__device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb) {
+// Rounds R0 .. R1-1 of the three draws of one window, advanced round by
+// round together: six independent 32x32->64 products per round. Round r uses
+// the key (key0 + r*kWeylA, key1 + r*kWeylB). Round 1 is identical for the
+// three draws (they differ only in counter word 1) and is computed once by
+// the compiler.
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds_x3(U4 (&c)[3], uint32_t key0, uint32_t key1) {
+    uint32_t ka = key0 + static_cast<uint32_t>(R0) * kWeylA;
+    uint32_t kb = key1 + static_cast<uint32_t>(R0) * kWeylB;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = R0; r < R1; ++r) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
@@ -98,13 +102,24 @@ __device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb
     }
 }
 
-template <int KDH, int KPH>
-__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
+// A window's draw is taken in two halves, rounds 0-4 and rounds 5-9 plus
+// the decisions, so that it can be spread over two barrier intervals.
+struct DrawState {
+    U4 x[3];
+};
+
+__device__ __forceinline__ DrawState draw_first_half(const LatDesc &ld, uint32_t k, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
-    U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
-    philox10_x3(x, ld.key0, ld.key1);
-    const U4 &d = x[0], &a = x[1], &r = x[2];
+    DrawState st{{U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}}};
+    philox_rounds_x3<0, 5>(st.x, ld.key0, ld.key1);
+    return st;
+}
+
+template <int KDH, int KPH>
+__device__ __forceinline__ Masks draw_second_half(const LatDesc &ld, DrawState st) {
+    philox_rounds_x3<5, 10>(st.x, ld.key0, ld.key1);
+    const U4 &d = st.x[0], &a = st.x[1], &r = st.x[2];
     const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
     const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
     Masks m;
@@ -116,6 +131,29 @@ __device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uin
     m.R.lo = r.x;
     m.R.hi = r.y;
     return m;
+}
+
+// Pin values in registers at this point of the program. Before a barrier,
+// the arithmetic that produces them cannot sink into the next interval;
+// after a barrier, the arithmetic that consumes them cannot be hoisted into
+// the previous one. Either move would take a draw out of the interval where
+// it overlaps the other team's work.
+__device__ __forceinline__ void pin(DrawState &st) {
+    asm volatile("" : "+v"(st.x[0].x), "+v"(st.x[0].y), "+v"(st.x[0].z), "+v"(st.x[0].w),
+                      "+v"(st.x[1].x), "+v"(st.x[1].y), "+v"(st.x[1].z), "+v"(st.x[1].w),
+                      "+v"(st.x[2].x), "+v"(st.x[2].y), "+v"(st.x[2].z), "+v"(st.x[2].w));
+}
+
+__device__ __forceinline__ void pin(uint32_t &v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ void pin(Masks &m) {
+    asm volatile("" : "+v"(m.D.lo), "+v"(m.D.hi), "+v"(m.Am.lo), "+v"(m.Am.hi), "+v"(m.R.lo),
+                      "+v"(m.R.hi));
+}
+
+template <int KDH, int KPH>
+__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
+    return draw_second_half<KDH, KPH>(ld, draw_first_half(ld, k, s));
 }
 
 // Bit-sliced attempt on one 32-bit half of a window; w[0] = site j-1,
@@ -153,14 +191,63 @@ __device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t 
     }
 }
 
+// Apply the attempt of substep site o to the lane's window in LDS (see
+// run_substeps for the two addressing cases).
+template <int N>
+__device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint32_t o,
+                                             uint32_t c, uint32_t col_in, bool ok_lo,
+                                             bool ok_hi, uint32_t trash, uint32_t B,
+                                             uint32_t ldw) {
+    uint32_t wl[N + 2], wh[N + 2];
+    if (o - 1u < B - 1u - N) {
+        // window rows o-1 .. o+N inside the lane's own column: one address
+        // plus multiples of the pitch (all but (N+1)/B of the substeps)
+        uint64_t *w = lds + ((o - 1u) * ldw + col_in);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k) {
+            const uint64_t v = w[k * ldw];
+            wl[k] = static_cast<uint32_t>(v);
+            wh[k] = static_cast<uint32_t>(v >> 32);
+        }
+        attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
+        attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k)
+            w[k * ldw] = static_cast<uint64_t>(wl[k]) | (static_cast<uint64_t>(wh[k]) << 32);
+    } else {
+        // window sites o-1 .. o+N of block c spill into block c-1 when o == 0
+        // and into block c+1 when o+N >= B
+        const bool ok = !(o == 0u && !ok_lo) && !(o + N >= B && !ok_hi);
+        const int col = static_cast<int>(ok ? c : trash);
+        int base[N + 2];
+        window_offsets<N>(o, B, ldw, base);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k) {
+            const uint64_t v = lds[base[k] + col];
+            wl[k] = static_cast<uint32_t>(v);
+            wh[k] = static_cast<uint32_t>(v >> 32);
+        }
+        attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
+        attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k)
+            lds[base[k] + col] = static_cast<uint64_t>(wl[k]) | (static_cast<uint64_t>(wh[k]) << 32);
+    }
+}
+
 // S substeps of one tile held in LDS (see the file comment), by two teams
 // of lanes, each with one lane per block. Team t applies the substeps
 // it = t, t+2, t+4, ...: in every interval between two barriers one team
-// updates the windows in LDS with masks it drew earlier while the other team
-// draws the masks of its own next substep. Each SIMD thus runs one wavefront
-// of either kind, and the short, latency-bound update path overlaps the
-// arithmetic of the draws. Each wavefront draws the local sites of 64
-// substeps at a time, one per lane, and reads them back with v_readlane.
+// updates the windows in LDS with masks it drew earlier and then starts the
+// draw of its substep it+2 (rounds 0-4, which fill the LDS latency of the
+// update), while the other team finishes the draw of its substep it+1
+// (rounds 5-9 and the decisions). A SIMD holds one wavefront of either kind,
+// and both have Philox rounds in flight in every interval. Each team runs its
+// own loop over pairs of intervals, so that every value has one definition
+// per pass and no register copies are needed; both loops pass the same
+// number of barriers. Draws past the phase end are computed and dropped.
+// Each wavefront draws the local sites of 64 substeps at a time, one per
+// lane, and reads them back with v_readlane.
 // Window rows o-1 .. o+N lie inside the lane's own column when
 // 1 <= o <= B-1-N; otherwise (a uniform branch, (N+1)/B of the substeps) the
 // window spills into a neighbouring column and each word has its own
@@ -174,58 +261,48 @@ __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, u
                                              uint32_t ldw) {
     const uint32_t lane = __lane_id();
     const bool active = c < ncols;
-    const bool first = c == 0u, last = c + 1u == ncols;
+    const bool ok_lo = active && c != 0u;        // a spill into block c-1 stays in the tile
+    const bool ok_hi = active && c + 1u != ncols;  // a spill into block c+1 stays in the tile
     const uint32_t col_in = active ? c : trash;  // column of a window inside one column
-    Masks cur{};
-    if (team == 0u) cur = window_masks<KDH, KPH>(ld, kg, s0);
-    for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
-        const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
-        const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
-        for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t it = it0 + j;
-            if ((it & 1u) == team) {
-                const uint32_t o = __builtin_amdgcn_readlane(sites, j);
-                uint32_t wl[N + 2], wh[N + 2];
-                if (o - 1u < B - 1u - N) {
-                    // window rows o-1 .. o+N inside the lane's own column: one
-                    // address plus multiples of the pitch (all but (N+1)/B of
-                    // the substeps)
-                    uint64_t *w = lds + ((o - 1u) * ldw + col_in);
-#pragma unroll
-                    for (int m = 0; m < N + 2; ++m) {
-                        const uint64_t v = w[m * ldw];
-                        wl[m] = static_cast<uint32_t>(v);
-                        wh[m] = static_cast<uint32_t>(v >> 32);
-                    }
-                    attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
-                    attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
-#pragma unroll
-                    for (int m = 0; m < N + 2; ++m)
-                        w[m * ldw] = static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
-                } else {
-                    // window sites o-1 .. o+N of block c spill into block c-1
-                    // when o == 0 and into block c+1 when o+N >= B
-                    const bool ok = active && !(o == 0u && first) && !(o + N >= B && last);
-                    const int col = static_cast<int>(ok ? c : trash);
-                    int base[N + 2];
-                    window_offsets<N>(o, B, ldw, base);
-#pragma unroll
-                    for (int m = 0; m < N + 2; ++m) {
-                        const uint64_t v = lds[base[m] + col];
-                        wl[m] = static_cast<uint32_t>(v);
-                        wh[m] = static_cast<uint32_t>(v >> 32);
-                    }
-                    attempt<N>(wl, cur.D.lo, cur.Am.lo, cur.R.lo);
-                    attempt<N>(wh, cur.D.hi, cur.Am.hi, cur.R.hi);
-#pragma unroll
-                    for (int m = 0; m < N + 2; ++m)
-                        lds[base[m] + col] =
-                            static_cast<uint64_t>(wl[m]) | (static_cast<uint64_t>(wh[m]) << 32);
-                }
-            } else if (it + 1u < S) {
-                cur = window_masks<KDH, KPH>(ld, kg, s0 + it + 1u);
+    if (team == 0u) {
+        Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
+        for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+            const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
+            const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+            for (uint32_t j = 0; j < n; j += 2u) {
+                // interval it0+j: apply substep it0+j, start the draw of it0+j+2
+                apply_window<N>(lds, cur, __builtin_amdgcn_readlane(sites, j), c, col_in, ok_lo,
+                                ok_hi, trash, B, ldw);
+                DrawState pend = draw_first_half(ld, kg, s0 + it0 + j + 2u);
+                pin(pend);
+                __syncthreads();
+                // interval it0+j+1: finish that draw
+                pin(pend);
+                cur = draw_second_half<KDH, KPH>(ld, pend);
+                pin(cur);
+                if (j + 1u < n) __syncthreads();
             }
-            __syncthreads();
+        }
+    } else {
+        DrawState pend = draw_first_half(ld, kg, s0 + 1u);
+        for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+            const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);
+            const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+            for (uint32_t j = 0; j < n; j += 2u) {
+                // interval it0+j: finish the draw of substep it0+j+1
+                Masks cur = draw_second_half<KDH, KPH>(ld, pend);
+                pin(cur);
+                __syncthreads();
+                // interval it0+j+1: apply it, start the draw of it0+j+3
+                uint32_t k = kg;
+                pin(k);
+                if (j + 1u < n)
+                    apply_window<N>(lds, cur, __builtin_amdgcn_readlane(sites, j + 1u), c, col_in,
+                                    ok_lo, ok_hi, trash, B, ldw);
+                pend = draw_first_half(ld, k, s0 + it0 + j + 3u);
+                pin(pend);
+                if (j + 1u < n) __syncthreads();
+            }
         }
     }
 }
@@ -380,8 +457,9 @@ __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
     }
 }
 
-// One workgroup per tile, two lanes per block (the two teams); LDS allows
-// one such workgroup per CU, two wavefronts per SIMD.
+// One workgroup per tile, two lanes per block (the two teams). At most two
+// wavefronts per SIMD: with 128-block tiles two workgroups share a CU, with
+// 256-block tiles one does.
 template <int N>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
