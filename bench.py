@@ -26,12 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Integer-VALU op model of one PCPD word-update (64 site updates): the VALU
-# instructions of the method's arithmetic as issued on gfx950, each one issue
-# slot per lane (32x32->64 products run at full rate on gfx950): three
-# Philox-4x32-10 draws = 53 products + 56 three-input XORs, two probability
-# decisions = 8, the bit-sliced PCPD attempt = 22. Addressing, register moves,
-# halo windows and tile copies are not counted.
-OPS_PER_WORD_UPDATE = 139
+# instructions of the method's per-site arithmetic as issued on gfx950, each
+# one issue slot per lane (32x32->64 products run at full rate on gfx950):
+# three Philox-4x32-10 draws = 47 products + 54 XORs, two probability
+# decisions = 8, the bit-sliced PCPD attempt = 22. Work that is uniform across
+# a wavefront (the counter words and keys of the first two rounds) runs on the
+# scalar unit and is not counted; neither are addressing, register moves, halo
+# windows and tile copies.
+OPS_PER_WORD_UPDATE = 131
 PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x 64 lanes x 2.4 GHz = 3.93e13 ops/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "brs_phase_pcpd_L2p20_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "sweep.hip")

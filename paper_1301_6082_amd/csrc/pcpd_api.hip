@@ -134,10 +134,8 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
 
 // Default shape: phases of four Monte Carlo steps (at most 256 substeps) and
 // the widest tile of at most 256 blocks that fits the LDS of one CU. At
-// B = 64 that is one workgroup of eight wavefronts per CU: two per SIMD, one
-// of each team, so every SIMD has one drawing and one updating wavefront in
-// every interval; whole tiles move in one round trip of 16-byte accesses.
-// Failing that, shorter phases.
+// B = 64 that is one workgroup of eight wavefronts per CU, two per SIMD, one
+// of each team. Failing that, shorter phases.
 bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_max) {
     uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(4 * B, 256));
     for (; pm >= 1; pm = pm / 2) {

@@ -91,9 +91,18 @@ __device__ __forceinline__ void philox_rounds_x3(U4 (&c)[3], uint32_t key0, uint
             const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
             const uint64_t pb = static_cast<uint64_t>(c[j].z) * kMulB;
             U4 nx;
-            nx.x = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c[j].y, ka, 0x96);
+            if (r < 2) {
+                // the first two rounds have operands that are uniform across the
+                // wavefront (counter words 1-3 and the key); plain XORs let the
+                // compiler keep those on the scalar unit, which the vector-only
+                // three-input XOR cannot
+                nx.x = static_cast<uint32_t>(pb >> 32) ^ c[j].y ^ ka;
+                nx.z = static_cast<uint32_t>(pa >> 32) ^ c[j].w ^ kb;
+            } else {
+                nx.x = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c[j].y, ka, 0x96);
+                nx.z = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c[j].w, kb, 0x96);
+            }
             nx.y = static_cast<uint32_t>(pb);
-            nx.z = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c[j].w, kb, 0x96);
             nx.w = static_cast<uint32_t>(pa);
             c[j] = nx;
         }
