@@ -132,17 +132,20 @@ bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, Phase
     return true;
 }
 
-// Default shape: phases of four Monte Carlo steps (at most 256 substeps) and
-// the widest tile of at most 256 blocks that fits the LDS of one CU. At
-// B = 64 that is one workgroup of eight wavefronts per CU, two per SIMD, one
-// of each team. Failing that, shorter phases.
+// Default shape: phases of two Monte Carlo steps (at most 128 substeps) and
+// the widest tile of at most 128 blocks that lets two workgroups share a CU
+// (half the LDS each), so that one workgroup's barriers and tile copies
+// overlap the other's arithmetic; failing that, any tile that fits.
 bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_max) {
-    uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(4 * B, 256));
+    uint32_t pm = std::max<uint32_t>(1, std::min<uint32_t>(2 * B, 128));
     for (; pm >= 1; pm = pm / 2) {
-        for (uint32_t cols = 256; cols >= 1; --cols) {
-            if (make_shape(n, B, cols, pm, shape)) {
-                *phase_max = pm;
-                return true;
+        for (uint32_t lds_cap : {pcpd::kMaxLdsBytes / 2, pcpd::kMaxLdsBytes}) {
+            for (uint32_t cols = 128; cols >= 1; --cols) {
+                if (make_shape(n, B, cols, pm, shape) &&
+                    pcpd::phase_lds_bytes(B, shape->ldw, pm) <= lds_cap) {
+                    *phase_max = pm;
+                    return true;
+                }
             }
         }
         if (pm == 1) break;

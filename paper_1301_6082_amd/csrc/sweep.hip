@@ -111,24 +111,13 @@ __device__ __forceinline__ void philox_rounds_x3(U4 (&c)[3], uint32_t key0, uint
     }
 }
 
-// A window's draw is taken in two halves, rounds 0-4 and rounds 5-9 plus
-// the decisions, so that it can be spread over two barrier intervals.
-struct DrawState {
-    U4 x[3];
-};
-
-__device__ __forceinline__ DrawState draw_first_half(const LatDesc &ld, uint32_t k, uint64_t s) {
+template <int KDH, int KPH>
+__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
-    DrawState st{{U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}}};
-    philox_rounds_x3<0, 5>(st.x, ld.key0, ld.key1);
-    return st;
-}
-
-template <int KDH, int KPH>
-__device__ __forceinline__ Masks draw_second_half(const LatDesc &ld, DrawState st) {
-    philox_rounds_x3<5, 10>(st.x, ld.key0, ld.key1);
-    const U4 &d = st.x[0], &a = st.x[1], &r = st.x[2];
+    U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
+    philox_rounds_x3<0, 10>(x, ld.key0, ld.key1);
+    const U4 &d = x[0], &a = x[1], &r = x[2];
     const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
     const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
     Masks m;
@@ -142,27 +131,12 @@ __device__ __forceinline__ Masks draw_second_half(const LatDesc &ld, DrawState s
     return m;
 }
 
-// Pin values in registers at this point of the program. Before a barrier,
-// the arithmetic that produces them cannot sink into the next interval;
-// after a barrier, the arithmetic that consumes them cannot be hoisted into
-// the previous one. Either move would take a draw out of the interval where
-// it overlaps the other team's work.
-__device__ __forceinline__ void pin(DrawState &st) {
-    asm volatile("" : "+v"(st.x[0].x), "+v"(st.x[0].y), "+v"(st.x[0].z), "+v"(st.x[0].w),
-                      "+v"(st.x[1].x), "+v"(st.x[1].y), "+v"(st.x[1].z), "+v"(st.x[1].w),
-                      "+v"(st.x[2].x), "+v"(st.x[2].y), "+v"(st.x[2].z), "+v"(st.x[2].w));
-}
-
-__device__ __forceinline__ void pin(uint32_t &v) { asm volatile("" : "+v"(v)); }
-
+// Pin the masks in registers at this point of the program. Before a barrier,
+// the arithmetic that produces them cannot sink into the next interval, where
+// it would no longer overlap the LDS latency of this interval's update.
 __device__ __forceinline__ void pin(Masks &m) {
     asm volatile("" : "+v"(m.D.lo), "+v"(m.D.hi), "+v"(m.Am.lo), "+v"(m.Am.hi), "+v"(m.R.lo),
                       "+v"(m.R.hi));
-}
-
-template <int KDH, int KPH>
-__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
-    return draw_second_half<KDH, KPH>(ld, draw_first_half(ld, k, s));
 }
 
 // Bit-sliced attempt on one 32-bit half of a window; w[0] = site j-1,
@@ -201,12 +175,14 @@ __device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t 
 }
 
 // Apply the attempt of substep site o to the lane's window in LDS (see
-// run_substeps for the two addressing cases).
-template <int N>
+// run_substeps for the two addressing cases). mid() runs after the window's
+// loads are issued and before their values are used: arithmetic placed there
+// fills the LDS latency.
+template <int N, typename Mid>
 __device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint32_t o,
                                              uint32_t c, uint32_t col_in, bool ok_lo,
                                              bool ok_hi, uint32_t trash, uint32_t B,
-                                             uint32_t ldw) {
+                                             uint32_t ldw, Mid &&mid) {
     uint32_t wl[N + 2], wh[N + 2];
     if (o - 1u < B - 1u - N) {
         // window rows o-1 .. o+N inside the lane's own column: one address
@@ -218,6 +194,8 @@ __device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint
             wl[k] = static_cast<uint32_t>(v);
             wh[k] = static_cast<uint32_t>(v >> 32);
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of mid()
+        mid();
         attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
         attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
 #pragma unroll
@@ -236,6 +214,8 @@ __device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint
             wl[k] = static_cast<uint32_t>(v);
             wh[k] = static_cast<uint32_t>(v >> 32);
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of mid()
+        mid();
         attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
         attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
 #pragma unroll
@@ -244,17 +224,29 @@ __device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint
     }
 }
 
+// True when the windows of two substeps with local sites oa and ob touch
+// disjoint sites: the cyclic distance of oa and ob within a block is at least
+// N+2, the window length. Every block uses the same local site, so the two
+// substeps then commute and may be applied in either order or together.
+template <int N>
+__device__ __forceinline__ bool windows_disjoint(uint32_t oa, uint32_t ob, uint32_t B) {
+    uint32_t d = ob - oa;
+    if (static_cast<int32_t>(d) < 0) d += B;  // (ob - oa) mod B, with oa, ob < B
+    const uint32_t e = B - d;                 // (oa - ob) mod B, or B when d == 0
+    return d >= N + 2u && e >= N + 2u;
+}
+
 // S substeps of one tile held in LDS (see the file comment), by two teams
-// of lanes, each with one lane per block. Team t applies the substeps
-// it = t, t+2, t+4, ...: in every interval between two barriers one team
-// updates the windows in LDS with masks it drew earlier and then starts the
-// draw of its substep it+2 (rounds 0-4, which fill the LDS latency of the
-// update), while the other team finishes the draw of its substep it+1
-// (rounds 5-9 and the decisions). A SIMD holds one wavefront of either kind,
-// and both have Philox rounds in flight in every interval. Each team runs its
-// own loop over pairs of intervals, so that every value has one definition
-// per pass and no register copies are needed; both loops pass the same
-// number of barriers. Draws past the phase end are computed and dropped.
+// of lanes, each with one lane per block; team t applies the substeps
+// it = t, t+2, t+4, ... Substeps are taken in pairs (it, it+1), it even:
+// when their windows are disjoint (windows_disjoint; at B = 64 and N = 2
+// all but 7 of 64 pairs) both teams apply their substep in the same interval
+// between two barriers; otherwise team 0 applies its substep in one interval
+// and team 1 in the next. Each team then draws the masks of its next
+// substep between the loads and the arithmetic of its update, which fills
+// the LDS latency. The two teams run
+// their own loops (no register copies between the branches) and pass the
+// same number of barriers. Draws past the phase end are computed and dropped.
 // Each wavefront draws the local sites of 64 substeps at a time, one per
 // lane, and reads them back with v_readlane.
 // Window rows o-1 .. o+N lie inside the lane's own column when
@@ -270,47 +262,70 @@ __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, u
                                              uint32_t ldw) {
     const uint32_t lane = __lane_id();
     const bool active = c < ncols;
-    const bool ok_lo = active && c != 0u;        // a spill into block c-1 stays in the tile
+    const bool ok_lo = active && c != 0u;          // a spill into block c-1 stays in the tile
     const bool ok_hi = active && c + 1u != ncols;  // a spill into block c+1 stays in the tile
-    const uint32_t col_in = active ? c : trash;  // column of a window inside one column
+    const uint32_t col_in = active ? c : trash;    // column of a window inside one column
+    // The masks alternate between two register sets (m0, m1) over a pair of
+    // pairs, so that no register copies are needed inside the loop.
+    Masks m0 = window_masks<KDH, KPH>(ld, kg, s0 + team), m1{};
     if (team == 0u) {
-        Masks cur = window_masks<KDH, KPH>(ld, kg, s0);
+        // one pair: apply substep it0+j, draw substep it0+j+2
+        auto step = [&](uint32_t sites, uint32_t it0, uint32_t n, uint32_t j, const Masks &use,
+                        Masks &make) {
+            const uint32_t oa = __builtin_amdgcn_readlane(sites, j);
+            const bool split = j + 1u < n &&
+                               !windows_disjoint<N>(oa, __builtin_amdgcn_readlane(sites, j + 1u), B);
+            auto draw = [&] {
+                make = window_masks<KDH, KPH>(ld, kg, s0 + it0 + j + 2u);
+                pin(make);
+            };
+            apply_window<N>(lds, use, oa, c, col_in, ok_lo, ok_hi, trash, B, ldw, draw);
+            __syncthreads();
+            if (split) __syncthreads();  // team 1 applies its substep alone
+        };
         for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
             const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
             const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
-            for (uint32_t j = 0; j < n; j += 2u) {
-                // interval it0+j: apply substep it0+j, start the draw of it0+j+2
-                apply_window<N>(lds, cur, __builtin_amdgcn_readlane(sites, j), c, col_in, ok_lo,
-                                ok_hi, trash, B, ldw);
-                DrawState pend = draw_first_half(ld, kg, s0 + it0 + j + 2u);
-                pin(pend);
-                __syncthreads();
-                // interval it0+j+1: finish that draw
-                pin(pend);
-                cur = draw_second_half<KDH, KPH>(ld, pend);
-                pin(cur);
-                if (j + 1u < n) __syncthreads();
+            uint32_t j = 0;
+            for (; j + 2u < n; j += 4u) {
+                step(sites, it0, n, j, m0, m1);
+                step(sites, it0, n, j + 2u, m1, m0);
+            }
+            if (j < n) {
+                step(sites, it0, n, j, m0, m1);
+                m0 = m1;
             }
         }
     } else {
-        DrawState pend = draw_first_half(ld, kg, s0 + 1u);
+        // one pair: apply substep it0+j+1 (if any), draw substep it0+j+3
+        auto step = [&](uint32_t sites, uint32_t it0, uint32_t n, uint32_t j, const Masks &use,
+                        Masks &make) {
+            const bool has_b = j + 1u < n;
+            const uint32_t ob = __builtin_amdgcn_readlane(sites, has_b ? j + 1u : j);
+            const bool split =
+                has_b && !windows_disjoint<N>(__builtin_amdgcn_readlane(sites, j), ob, B);
+            if (split) __syncthreads();  // after team 0's substep
+            auto draw = [&] {
+                make = window_masks<KDH, KPH>(ld, kg, s0 + it0 + j + 3u);
+                pin(make);
+            };
+            if (has_b)
+                apply_window<N>(lds, use, ob, c, col_in, ok_lo, ok_hi, trash, B, ldw, draw);
+            else
+                draw();
+            __syncthreads();
+        };
         for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
             const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);
             const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
-            for (uint32_t j = 0; j < n; j += 2u) {
-                // interval it0+j: finish the draw of substep it0+j+1
-                Masks cur = draw_second_half<KDH, KPH>(ld, pend);
-                pin(cur);
-                __syncthreads();
-                // interval it0+j+1: apply it, start the draw of it0+j+3
-                uint32_t k = kg;
-                pin(k);
-                if (j + 1u < n)
-                    apply_window<N>(lds, cur, __builtin_amdgcn_readlane(sites, j + 1u), c, col_in,
-                                    ok_lo, ok_hi, trash, B, ldw);
-                pend = draw_first_half(ld, k, s0 + it0 + j + 3u);
-                pin(pend);
-                if (j + 1u < n) __syncthreads();
+            uint32_t j = 0;
+            for (; j + 2u < n; j += 4u) {
+                step(sites, it0, n, j, m0, m1);
+                step(sites, it0, n, j + 2u, m1, m0);
+            }
+            if (j < n) {
+                step(sites, it0, n, j, m0, m1);
+                m0 = m1;
             }
         }
     }
