@@ -12,6 +12,8 @@
 // absorbed every influence from outside the tile, because one attempt reads
 // and writes only sites j-1..j+n; halo windows are computed redundantly with
 // the same counter-based draws as their owners, so the interior is exact.
+// Two consecutive substeps whose windows touch disjoint sites commute; such
+// pairs are applied in one interval between workgroup barriers.
 //
 // LDS layout: offset-major, word (block c, local site o) at o*ldw + c. All
 // lanes of a substep touch the same row o, consecutive columns: no bank
@@ -75,17 +77,13 @@ struct Masks {
     W2 D, Am, R;
 };
 
-// Rounds R0 .. R1-1 of the three draws of one window, advanced round by
-// round together: six independent 32x32->64 products per round. Round r uses
-// the key (key0 + r*kWeylA, key1 + r*kWeylB). Round 1 is identical for the
-// three draws (they differ only in counter word 1) and is computed once by
-// the compiler.
-template <int R0, int R1>
-__device__ __forceinline__ void philox_rounds_x3(U4 (&c)[3], uint32_t key0, uint32_t key1) {
-    uint32_t ka = key0 + static_cast<uint32_t>(R0) * kWeylA;
-    uint32_t kb = key1 + static_cast<uint32_t>(R0) * kWeylB;
+// The ten rounds of the three draws of one window, advanced round by round
+// together: six independent 32x32->64 products per round. The first round's
+// products are identical for the three draws (they differ only in counter
+// word 1) and are computed once by the compiler.
+__device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb) {
 #pragma unroll
-    for (int r = R0; r < R1; ++r) {
+    for (int r = 0; r < 10; ++r) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
@@ -116,7 +114,7 @@ __device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uin
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
     U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
-    philox_rounds_x3<0, 10>(x, ld.key0, ld.key1);
+    philox10_x3(x, ld.key0, ld.key1);
     const U4 &d = x[0], &a = x[1], &r = x[2];
     const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
     const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
