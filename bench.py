@@ -9,10 +9,15 @@ end; consecutive steps continue the same trajectory, so warmup + timed steps
 cover a prefix of the 10^5-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mc-per-step M]
+                    [--workload cfg2|cfg3|cfg4] [--autotune]
 
 Prints one JSON line. Also reports the dominant kernel (the phase kernel of
 the sweep) against the integer-VALU roofline, and the CPU oracle on a bounded
-sample of the same workload.
+sample of the same workload. The default workload is the one above; cfg3 (512
+batched PCPD rings of uneven length, one plane) and cfg4 (TCPD, 8 rings of
+2^18 sites, one plane) report the same metric on those workloads, without the
+CPU leg. --autotune times the library's tile shapes on the workload before the
+timed region.
 """
 from __future__ import annotations
 
@@ -25,15 +30,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer-VALU op model of one PCPD word-update (64 site updates): the VALU
+# Integer-VALU op model of one word-update (64 site updates): the VALU
 # instructions of the method's per-site arithmetic as issued on gfx950, each
 # one issue slot per lane (32x32->64 products run at full rate on gfx950):
 # three Philox-4x32-10 draws = 47 products + 54 XORs, two probability
-# decisions = 8, the bit-sliced PCPD attempt = 22. Work that is uniform across
-# a wavefront (the counter words and keys of the first two rounds) runs on the
-# scalar unit and is not counted; neither are addressing, register moves, halo
-# windows and tile copies.
-OPS_PER_WORD_UPDATE = 131
+# decisions = 8, and the bit-sliced attempt = 20 (DP), 22 (PCPD) or 26 (TCPD).
+# Work that is uniform across a wavefront (the counter words and keys of the
+# first two rounds) runs on the scalar unit and is not counted; neither are
+# addressing, register moves, halo windows and tile copies.
+OPS_PER_WORD_UPDATE = {1: 129, 2: 131, 3: 135}
 PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x 64 lanes x 2.4 GHz = 3.93e13 ops/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "brs_phase_pcpd_L2p20_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "sweep.hip")
@@ -50,6 +55,9 @@ def parse():
                     help="(instance, plane) units for the oracle timing; 0 = one per host thread")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device three times first (counter calibration)")
+    ap.add_argument("--workload", choices=("cfg2", "cfg3", "cfg4"), default="cfg2")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the library's tile shapes on the workload first (untimed)")
     return ap.parse_args()
 
 
@@ -116,7 +124,7 @@ def main():
     torch.cuda.set_device(0)
     M = args.mc_per_step
     total_steps = (args.warmup + args.steps) * M
-    wl = workloads.cfg2()
+    wl = {"cfg2": workloads.cfg2, "cfg3": workloads.cfg3, "cfg4": workloads.cfg4}[args.workload]()
     rec_times = [t for t in wl.times]
     su_per_mc = sum(64 * wl.planes * inst.L for inst in wl.instances)
 
@@ -130,6 +138,8 @@ def main():
         del src, dst
 
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
+    if args.autotune:
+        sim.autotune()
 
     def step_times(k):
         lo, hi = k * M, (k + 1) * M
@@ -159,14 +169,33 @@ def main():
     tuning = sim.get_tuning()
     launch_ms = kernel_ms / launches
     word_updates = site_updates / 64          # interior windows, all launches
-    ops_per_launch = OPS_PER_WORD_UPDATE * word_updates / launches
+    ops_word = OPS_PER_WORD_UPDATE[wl.model]
+    ops_per_launch = ops_word * word_updates / launches
     achieved = ops_per_launch / (launch_ms * 1e-3)
-    traffic = kernel_traffic(tuning)
-    rho = counts[-1, :, :, 0].astype(np.float64).sum(axis=1) / (64 * wl.planes * (1 << 20))
+    # the committed counter profile covers the default workload only
+    traffic = kernel_traffic(tuning) if args.workload == "cfg2" else None
+    Ls = np.array([inst.L for inst in wl.instances], dtype=np.float64)
+    rho = counts[-1, :, :, 0].astype(np.float64).sum(axis=1) / (64 * wl.planes * Ls)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "cfg2":
         cpu = cpu_baseline(wl, args.cpu_sample_units)
+
+    if args.workload == "cfg2":
+        config = {"workload": wl.name, "L": 1 << 20, "planes": wl.planes,
+                  "samples_per_instance": 64 * wl.planes, "instances": len(wl.instances),
+                  "d": 0.1, "p": "linspace(0.05,0.20,16)", "B": wl.B}
+    else:
+        ds = sorted({inst.d for inst in wl.instances})
+        config = {"workload": wl.name, "model": {1: "DP", 2: "PCPD", 3: "TCPD"}[wl.model],
+                  "L": [int(Ls.min()), int(Ls.max())], "total_sites": int(Ls.sum()),
+                  "planes": wl.planes, "samples_per_instance": 64 * wl.planes,
+                  "instances": len(wl.instances), "d": ds if len(ds) > 1 else ds[0],
+                  "p": [round(min(i.p for i in wl.instances), 4),
+                        round(max(i.p for i in wl.instances), 4)], "B": wl.B}
+    config.update({"mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
+                   "records": "the workload's log-spaced record times, plus each step end",
+                   "tile_cols": tuning[0], "phase_max": tuning[1], "autotuned": args.autotune})
 
     out = {
         "metric": "site-updates/sec (samples x sites x MC steps) at 1 GPU",
@@ -181,18 +210,13 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "L": 1 << 20, "planes": wl.planes,
-                   "samples_per_instance": 64 * wl.planes, "instances": len(wl.instances),
-                   "d": 0.1, "p": "linspace(0.05,0.20,16)", "B": wl.B,
-                   "mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
-                   "records": "64 log-spaced times of a 1e5-step run, plus each step end",
-                   "tile_cols": tuning[0], "phase_max": tuning[1]},
+        "config": config,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)",
                      "frac": achieved / PEAK_SLOTS, "traffic": traffic,
-                     "kernel": "brs_phase<2>", "launch_ms": launch_ms, "launches": launches,
-                     "ops_per_word_update": OPS_PER_WORD_UPDATE,
-                     "site_updates_per_s_at_peak": PEAK_SLOTS / OPS_PER_WORD_UPDATE * 64,
+                     "kernel": f"brs_phase<{wl.model}>", "launch_ms": launch_ms,
+                     "launches": launches, "ops_per_word_update": ops_word,
+                     "site_updates_per_s_at_peak": PEAK_SLOTS / ops_word * 64,
                      "kernel_share_of_wall": kernel_ms * 1e-3 / elapsed},
         "cpu_baseline": cpu,
         "rho_at_end": [round(float(x), 5) for x in rho],
