@@ -110,3 +110,24 @@ def test_compare_end_to_end_small(ps):
         assert s[side]["site_updates"] == s[side]["runs"] * spec.site_updates()
     assert s["plain"]["runs"] == 5
     assert 1 <= s["surrogate"]["runs"] <= 31
+
+
+def test_classes_bracket_the_published_critical_points(ps):
+    """A weak physics pin against the paper's published p_c (Sec. 5.3,
+    Figs. 5-6; tests/golden/published_pc.json): on rings of the paper's size,
+    runs 0.01 below p_c stay active and runs 0.01 above it decay. The sweep is
+    a variant of the paper's update order and T is finite, so only this wide
+    margin is checked."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "published_pc.json")))
+    spec = ps.RunSpec(L=gold["L"], planes=1, steps=100_000, records=64, tune=False)
+    probes = []
+    for k, pt in enumerate(gold["points"]):
+        probes += [(pt["p_c"] - 0.01, pt["d"], k), (pt["p_c"] + 0.01, pt["d"], k)]
+    t, rhos = ps.simulate_curves(spec, probes)
+    for (p, d, _), rho in zip(probes, rhos):
+        below = p < next(pt["p_c"] for pt in gold["points"] if pt["d"] == d)
+        print(f"[physics] d={d} p={p:.6f} inactive={ps.classify(t, rho)} rho(T)={rho[-1]:.4g}",
+              flush=True)
+        assert ps.classify(t, rho) == (not below)

@@ -126,10 +126,19 @@ def test_sample_subsets_evolve_independently():
         assert (part.n[:, b] == full.n[:, b]).all()
 
 
-@pytest.mark.parametrize("d,p_active,p_inactive", [(0.25, 0.05, 0.30), (0.75, 0.12, 0.35)])
-def test_phases_on_either_side_of_the_papers_critical_rate(d, p_active, p_inactive):
-    """Paper Sec. 5.3: p_c(d=0.25) = 0.125141, p_c(d=0.75) = 0.191789. Well
+def _published_pc():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "published_pc.json")
+    return [(pt["d"], pt["p_c"]) for pt in json.load(open(path))["points"]]
+
+
+@pytest.mark.parametrize("d,p_c", _published_pc())
+def test_phases_on_either_side_of_the_papers_critical_rate(d, p_c):
+    """Paper Sec. 5.3 (Figs. 5-6; tests/golden/published_pc.json): p_c(d=0.25)
+    = 0.125141, p_c(d=0.75) = 0.191789. On a small ring and a short run, well
     below p_c the density stays finite; well above it decays towards zero."""
+    p_active, p_inactive = p_c - 0.07, p_c + 0.16
     L = 1024
     act = oracle.simulate(oracle.Run(L=L, p=p_active, d=d, times=[1500]))
     ina = oracle.simulate(oracle.Run(L=L, p=p_inactive, d=d, times=[1500]))
