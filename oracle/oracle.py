@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcpd_oracle.c")
 _LIB = os.path.join(_HERE, "libpcpd_oracle.so")
 
-MODEL_N = {"dp": 1, "pcpd": 2, "tcpd": 3}
+MODEL_N = {"dp": 1, "pcpd": 2, "tcpd": 3, "qcpd": 4}
 INIT_KIND = {"full": 0, "empty": 1, "host": 2}
 
 
@@ -61,7 +61,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         u32, u64 = ctypes.c_uint32, ctypes.c_uint64

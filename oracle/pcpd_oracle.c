@@ -1,8 +1,9 @@
 /*
  * pcpd_oracle.c -- plain CPU oracle for the multispin Monte Carlo sweep of the
  * 1+1-dimensional n-tuple contact process with diffusion (DP n=1, PCPD n=2,
- * TCPD n=3), from R.D. Schram, "Reaction-diffusion model Monte Carlo
- * simulations on the GPU" (arXiv:1301.6082).
+ * TCPD n=3, QCPD n=4), from R.D. Schram, "Reaction-diffusion model Monte
+ * Carlo simulations on the GPU" (arXiv:1301.6082). The paper develops the
+ * PCPD and names DP, TCPD and QCPD as direct extensions (Sec. 1).
  *
  * TEST INFRASTRUCTURE. This file is the checker, not the product: only the
  * test suite, the smoke check and the CPU-baseline leg of the benchmark may
@@ -214,7 +215,7 @@ uint32_t orc_rule_window(int n, uint32_t window, int D, int A, int R)
 }
 
 typedef struct {
-    int32_t n;          /* tuple size: 1 DP, 2 PCPD, 3 TCPD */
+    int32_t n;          /* tuple size: 1 DP, 2 PCPD, 3 TCPD, 4 QCPD */
     uint32_t B;         /* block width */
     uint64_t L;         /* ring length */
     uint32_t seed;      /* Philox key word 0 */
@@ -242,7 +243,7 @@ int orc_simulate(const orc_params *P)
     uint32_t r, k;
     uint64_t nblocks;
 
-    if (!P || P->n < 1 || P->n > 3 || P->B < (uint32_t)(P->n + 2) || P->L < P->B ||
+    if (!P || P->n < 1 || P->n > 4 || P->B < (uint32_t)(P->n + 2) || P->L < P->B ||
         P->L % P->B != 0 || (P->L / P->B) > 0xffffffffull || P->plane >= (1u << 29))
         return -1;
     Kd = orc_threshold(P->d);

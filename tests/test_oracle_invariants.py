@@ -15,7 +15,7 @@ def _rand_init(L, density, seed):
     return workloads.random_lattice(L, 1, density, seed)
 
 
-@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd"])
+@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd", "qcpd"])
 def test_pure_diffusion_conserves_particles(model):
     L = 256
     init = _rand_init(L, 0.4, 1)
@@ -28,14 +28,15 @@ def test_pure_diffusion_conserves_particles(model):
     assert start.sum() == per_sample0.sum()
 
 
-def test_pure_annihilation_never_creates_particles():
+@pytest.mark.parametrize("model,n_tuple", [("pcpd", 2), ("qcpd", 4)])
+def test_pure_annihilation_never_creates_particles(model, n_tuple):
     L = 512
-    r = oracle.simulate(oracle.Run(L=L, p=1.0, d=0.0, init="host",
+    r = oracle.simulate(oracle.Run(model=model, L=L, p=1.0, d=0.0, init="host",
                                    init_words=_rand_init(L, 0.7, 2),
                                    times=list(range(0, 31))))
     n, _ = _per_sample(r)
     assert (np.diff(n, axis=0) <= 0).all()
-    assert (np.diff(n, axis=0) % 2 == 0).all()   # pairs vanish two at a time
+    assert (np.diff(n, axis=0) % n_tuple == 0).all()   # tuples vanish whole
     assert (np.diff(n, axis=0) < 0).any()
 
 
@@ -49,7 +50,7 @@ def test_pure_fission_never_removes_particles():
     assert (np.diff(n, axis=0) > 0).any()
 
 
-@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd"])
+@pytest.mark.parametrize("model", ["dp", "pcpd", "tcpd", "qcpd"])
 def test_empty_lattice_is_absorbing(model):
     r = oracle.simulate(oracle.Run(model=model, L=256, p=0.1, d=0.5, init="empty",
                                    times=[1, 5, 20]))
@@ -79,6 +80,20 @@ def test_two_particles_are_frozen_in_number_for_tcpd():
     r = oracle.simulate(oracle.Run(model="tcpd", L=L, p=0.05, d=0.3, init="host",
                                    init_words=init, times=list(range(1, 40, 3))))
     assert (r.n == 2).all()
+
+
+def test_three_particles_are_frozen_in_number_for_qcpd():
+    """QCPD reacts only on four adjacent particles, so three particles only
+    diffuse."""
+    L = 128
+    init = np.zeros(L, dtype=np.uint64)
+    rng = np.random.default_rng(6)
+    for b in range(64):
+        for i in rng.choice(L, size=3, replace=False):
+            init[i] |= np.uint64(1) << np.uint64(b)
+    r = oracle.simulate(oracle.Run(model="qcpd", L=L, p=0.05, d=0.3, init="host",
+                                   init_words=init, times=list(range(1, 40, 3))))
+    assert (r.n == 3).all()
 
 
 def test_dp_single_particle_can_spread():

@@ -5,8 +5,9 @@ The rewrite form below is a second reading of the model, independent of the
 oracle's if/else code: a decision selects one reaction (diffusion, pair
 annihilation, fission right, fission left); the reaction fires only where its
 left-hand pattern matches the window, and then its right-hand side replaces
-the matched sites. For DP and TCPD the reaction lists are the n-tuple
-analogues: DP A->0, A0->AA, 0A->AA; TCPD AAA->000, AAA0->AAAA, 0AAA->AAAA."""
+the matched sites. For DP, TCPD and QCPD (paper Sec. 1) the reaction lists are
+the n-tuple analogues: DP A->0, A0->AA, 0A->AA; TCPD AAA->000, AAA0->AAAA,
+0AAA->AAAA; QCPD AAAA->0000, AAAA0->AAAAA, 0AAAA->AAAAA."""
 import itertools
 
 import pytest
@@ -52,7 +53,7 @@ def from_str(s):
     return sum(1 << i for i, c in enumerate(s) if c == "A")
 
 
-@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
 def test_rule_table_exhaustive(n):
     width = n + 2
     for state in range(1 << width):

@@ -67,7 +67,7 @@ def _substep_matrix(n, L, B, p, d):
 
 def _empirical(n, L, B, p, d, init_state, runs, steps=1, seed=5):
     init = np.array([((init_state >> j) & 1) for j in range(L)], dtype=np.uint64)
-    model = {1: "dp", 2: "pcpd", 3: "tcpd"}[n]
+    model = {1: "dp", 2: "pcpd", 3: "tcpd", 4: "qcpd"}[n]
     rs = [oracle.Run(model=model, B=B, L=L, seed=seed, stream=r, plane=0, p=p, d=d,
                      samples=1, init="host", init_words=init, times=[steps])
           for r in range(runs)]
@@ -104,6 +104,8 @@ CASES = [
     (2, 8, 8, 0.15, 0.6, 0b11100110, 1),
     (3, 5, 5, 0.3, 0.2, 0b01110, 1),
     (3, 7, 7, 0.25, 0.35, 0b1110111, 1),
+    (4, 6, 6, 0.3, 0.3, 0b011110, 1),
+    (4, 7, 7, 0.2, 0.4, 0b1111011, 1),
     (1, 4, 4, 0.4, 0.3, 0b0010, 1),
     (1, 6, 3, 0.3, 0.2, 0b010010, 1),
 ]
