@@ -34,11 +34,12 @@ sys.path.insert(0, ROOT)
 # instructions of the method's per-site arithmetic as issued on gfx950, each
 # one issue slot per lane (32x32->64 products run at full rate on gfx950):
 # three Philox-4x32-10 draws = 47 products + 54 XORs, two probability
-# decisions = 8, and the bit-sliced attempt = 20 (DP), 22 (PCPD) or 26 (TCPD).
+# decisions = 8, and the bit-sliced attempt = 20 (DP), 22 (PCPD), 26 (TCPD) or
+# 30 (QCPD).
 # Work that is uniform across a wavefront (the counter words and keys of the
 # first two rounds) runs on the scalar unit and is not counted; neither are
 # addressing, register moves, halo windows and tile copies.
-OPS_PER_WORD_UPDATE = {1: 129, 2: 131, 3: 135}
+OPS_PER_WORD_UPDATE = {1: 129, 2: 131, 3: 135, 4: 139}
 PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x 64 lanes x 2.4 GHz = 3.93e13 ops/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "brs_phase_pcpd_L2p20_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "sweep.hip")
@@ -187,7 +188,7 @@ def main():
                   "d": 0.1, "p": "linspace(0.05,0.20,16)", "B": wl.B}
     else:
         ds = sorted({inst.d for inst in wl.instances})
-        config = {"workload": wl.name, "model": {1: "DP", 2: "PCPD", 3: "TCPD"}[wl.model],
+        config = {"workload": wl.name, "model": {1: "DP", 2: "PCPD", 3: "TCPD", 4: "QCPD"}[wl.model],
                   "L": [int(Ls.min()), int(Ls.max())], "total_sites": int(Ls.sum()),
                   "planes": wl.planes, "samples_per_instance": 64 * wl.planes,
                   "instances": len(wl.instances), "d": ds if len(ds) > 1 else ds[0],

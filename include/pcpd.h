@@ -1,14 +1,17 @@
 /*
  * pcpd.h -- C ABI of libpcpd, the MI355X (gfx950) multispin Monte Carlo sweep
  * of 1+1-dimensional reaction-diffusion models: directed percolation (DP),
- * the pair contact process with diffusion (PCPD) and the triplet contact
- * process with diffusion (TCPD), after R.D. Schram, arXiv:1301.6082.
+ * the pair contact process with diffusion (PCPD), and the triplet and
+ * quadruplet contact processes with diffusion (TCPD, QCPD), after R.D.
+ * Schram, arXiv:1301.6082 (which develops the PCPD and names the others as
+ * direct extensions, Sec. 1).
  *
  * What the library computes (all of it on the GPU):
  *   - The model (paper Sec. 2, eq. (1)): on a ring of L sites, attempted
  *     reactions AA0 -> AAA and 0AA -> AAA each with rate (1-p)(1-d)/2,
  *     AA -> 00 with rate p(1-d), A0 <-> 0A with rate d. The n-tuple form
- *     generalises "AA" to n particles (DP n = 1, PCPD n = 2, TCPD n = 3).
+ *     generalises "AA" to n particles (DP n = 1, PCPD n = 2, TCPD n = 3,
+ *     QCPD n = 4).
  *   - One attempt (paper Algorithm 1): diffusion swaps sites j and j+1 with
  *     probability d; otherwise an n-tuple at j..j+n-1 annihilates with
  *     probability p, else a particle is created at j+n (R = 1, "high") or
@@ -65,7 +68,7 @@ typedef enum {
     PCPD_EOVERFLOW = -5   /* the substep counter t*B would leave 64 bits */
 } pcpd_status;
 
-typedef enum { PCPD_DP = 1, PCPD_PCPD = 2, PCPD_TCPD = 3 } pcpd_model; /* = tuple size n */
+typedef enum { PCPD_DP = 1, PCPD_PCPD = 2, PCPD_TCPD = 3, PCPD_QCPD = 4 } pcpd_model; /* = tuple size n */
 
 typedef enum { PCPD_INIT_FULL = 0, PCPD_INIT_EMPTY = 1, PCPD_INIT_HOST = 2 } pcpd_init_kind;
 

@@ -96,7 +96,7 @@ bool rate_ok(double q) { return std::isfinite(q) && q >= 0.0 && q <= 1.0; }
 
 int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst) {
     if (!cfg || !inst || n_inst == 0) return PCPD_EINVAL;
-    if (cfg->model < 1 || cfg->model > 3) return PCPD_EINVAL;
+    if (cfg->model < 1 || cfg->model > 4) return PCPD_EINVAL;
     const uint32_t n = static_cast<uint32_t>(cfg->model);
     if (cfg->B < n + 2 || cfg->planes == 0 || cfg->planes >= (1u << 29)) return PCPD_EINVAL;
     uint64_t total = 0;

@@ -627,6 +627,7 @@ hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc
         case 1: return launch_phase_n<1>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
         case 2: return launch_phase_n<2>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
         case 3: return launch_phase_n<3>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
+        case 4: return launch_phase_n<4>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libpcpd.so")
 
 OPT_GRAPH = 1
 PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
-DP, PCPD, TCPD = 1, 2, 3
+DP, PCPD, TCPD, QCPD = 1, 2, 3, 4
 INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
 
 u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32

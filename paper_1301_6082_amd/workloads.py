@@ -16,7 +16,7 @@ from typing import List
 
 import numpy as np
 
-DP, PCPD, TCPD = 1, 2, 3
+DP, PCPD, TCPD, QCPD = 1, 2, 3, 4
 INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
 
 

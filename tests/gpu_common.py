@@ -6,7 +6,7 @@ import numpy as np
 
 from oracle import oracle
 
-MODEL_NAME = {1: "dp", 2: "pcpd", 3: "tcpd"}
+MODEL_NAME = {1: "dp", 2: "pcpd", 3: "tcpd", 4: "qcpd"}
 
 
 def sample_bits(words: np.ndarray) -> np.ndarray:

@@ -59,8 +59,8 @@ def _inst(mod, p=0.1, d=0.5, L=1024, init=0, words=None):
 
 
 BAD = [
-    dict(cfg=dict(model=0)), dict(cfg=dict(model=4)), dict(cfg=dict(B=3)),
-    dict(cfg=dict(model=3, B=4)), dict(cfg=dict(planes=0)), dict(cfg=dict(planes=1 << 29)),
+    dict(cfg=dict(model=0)), dict(cfg=dict(model=5)), dict(cfg=dict(B=3)),
+    dict(cfg=dict(model=3, B=4)), dict(cfg=dict(model=4, B=5)), dict(cfg=dict(planes=0)), dict(cfg=dict(planes=1 << 29)),
     dict(inst=dict(p=-0.1)), dict(inst=dict(p=1.5)), dict(inst=dict(d=float("nan"))),
     dict(inst=dict(d=float("inf"))), dict(inst=dict(L=100)), dict(inst=dict(L=32)),
     dict(inst=dict(L=0)), dict(inst=dict(init=3)), dict(inst=dict(init=2, words=None)),

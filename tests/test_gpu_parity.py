@@ -58,8 +58,8 @@ def test_several_tiles_and_ragged_tail(pcpd):
     _compare_full(pcpd, 2, 64, 2, 7, insts, [0, 1, 3, 12])
 
 
-@pytest.mark.parametrize("model", [1, 3])
-def test_dp_and_tcpd_parity(pcpd, model):
+@pytest.mark.parametrize("model", [1, 3, 4])
+def test_dp_tcpd_qcpd_parity(pcpd, model):
     insts = [Instance(0.08, 0.5, 64 * 260, 1), Instance(0.3, 0.1, 64 * 17, 2)]
     _compare_full(pcpd, model, 64, 1, 3, insts, [2, 9])
 
@@ -71,14 +71,16 @@ def test_tile_shape_does_not_change_results(pcpd, tuning):
 
 
 @pytest.mark.parametrize("L,B,model", [(4, 4, 2), (5, 5, 2), (8, 4, 2), (6, 6, 3), (3, 3, 1),
-                                       (192, 192, 2), (96, 32, 2), (1000, 8, 2)])
+                                       (192, 192, 2), (96, 32, 2), (1000, 8, 2), (6, 6, 4),
+                                       (7, 7, 4), (12, 6, 4), (1200, 12, 4)])
 def test_small_rings_and_block_widths(pcpd, L, B, model):
     insts = [Instance(0.2, 0.3, L, 0), Instance(0.05, 0.9, L, 1)]
     _compare_full(pcpd, model, B, 2, 1, insts, [1, 2, 17])
 
 
 @pytest.mark.parametrize("L,B,model", [(32 * 700, 32, 2), (96 * 150, 96, 2), (16 * 1500, 16, 3),
-                                       (64 * 700, 64, 1), (15 * 1400, 15, 2), (9 * 2000, 9, 3)])
+                                       (64 * 700, 64, 1), (15 * 1400, 15, 2), (9 * 2000, 9, 3),
+                                       (64 * 700, 64, 4), (11 * 1800, 11, 4)])
 def test_block_widths_over_many_tiles(pcpd, L, B, model):
     """Block widths other than 64 over many tiles per ring: even widths move
     tiles as 16-byte site pairs, odd widths one word at a time."""
