@@ -160,6 +160,20 @@ def match_index(ys, sim_log10, late) -> int:
     return int(np.argmin(err))
 
 
+def restrict_to_domain(ys, cls, grid: Grid, domain=None):
+    """Outside the p range the network was trained on, its predictions are
+    extrapolations. There its classes are taken as active below the range and
+    inactive above it, and its curves are kept out of calibration matches."""
+    if domain is None:
+        return ys, cls
+    below, above = grid.p < domain[0], grid.p > domain[1]
+    ys = np.array(ys, float)
+    cls = np.array(cls, bool)
+    cls[below], cls[above] = False, True
+    ys[below | above] = np.inf
+    return ys, cls
+
+
 def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
                     calibrated: int = CALIBRATED_PROBES):
     """Bracket search whose probes the surrogate places. `ys` [grid, times]
@@ -296,12 +310,13 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
 
 def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
                      lo: int = 0, hi: Optional[int] = None, predictor=None,
-                     calibrated: int = CALIBRATED_PROBES):
+                     calibrated: int = CALIBRATED_PROBES, domain=None):
     """The surrogate-guided search alone; `predictor(d, idx)` -> (log10 rho
-    [len(idx), times], classes) replaces the network (tests)."""
+    [len(idx), times], classes) replaces the network (tests). `domain` is the
+    network's training p range (see restrict_to_domain)."""
     hi = len(grid) - 1 if hi is None else hi
     predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
-    ys, cls = predictor(d, list(range(len(grid))))
+    ys, cls = restrict_to_domain(*predictor(d, list(range(len(grid)))), grid, domain)
     gen = surrogate_steps(ys, cls, grid, spec.times(), lo, hi, calibrated)
     res = drive({"surrogate": (gen, d, d_idx)}, spec, grid, _sequential(runner))
     return res["surrogate"]
@@ -373,47 +388,59 @@ def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-
 
 def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
                     train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
-                    epochs: int = 150, seed: int = 2013, log=print, p_range=(0.04, 0.30)):
+                    epochs: int = 150, seed: int = 2013, log=print, p_range=(0.04, 0.30),
+                    data_path: Optional[str] = None):
     """Simulate the training curves (batched runs at the search's horizon) and
-    train a surrogate on them. Returns (net, training summary)."""
+    train a surrogate on them. Returns (net, training summary). With
+    `data_path`, the simulated set (features, targets, mask, site updates) is
+    read from that .npz file if it exists, else written there."""
+    import os
     import time
 
     from . import pcpd
 
     spec = spec or RunSpec()
     t0 = time.perf_counter()
-    xs, ys, ms, train_su = [], [], [], 0
-    for b in range(train_batches):
-        insts = training_batch(train_count, spec, seed + b, d_values=d_values, L_range=train_L,
-                               p_range=p_range)
-        x, y, m, su = simulate_training_set(insts, spec, seed + b)
-        xs.append(x), ys.append(y), ms.append(m)
-        train_su += su
-        log(f"training batch {b + 1}/{train_batches}: {len(insts)} curves, "
-            f"{time.perf_counter() - t0:.1f} s")
-    x, y, m = np.concatenate(xs), np.concatenate(ys), np.concatenate(ms)
+    if data_path and os.path.exists(data_path):
+        with np.load(data_path) as z:
+            x, y, m, train_su = z["x"], z["y"], z["m"], int(z["site_updates"])
+        log(f"training set read from {data_path}: {len(y)} rows")
+    else:
+        xs, ys, ms, train_su = [], [], [], 0
+        for b in range(train_batches):
+            insts = training_batch(train_count, spec, seed + b, d_values=d_values,
+                                   L_range=train_L, p_range=p_range)
+            x, y, m, su = simulate_training_set(insts, spec, seed + b)
+            xs.append(x), ys.append(y), ms.append(m)
+            train_su += su
+            log(f"training batch {b + 1}/{train_batches}: {len(insts)} curves, "
+                f"{time.perf_counter() - t0:.1f} s")
+        x, y, m = np.concatenate(xs), np.concatenate(ys), np.concatenate(ms)
+        if data_path:
+            np.savez(data_path, x=x, y=y, m=m, site_updates=np.int64(train_su))
     t_data = time.perf_counter() - t0
     net = pcpd.Surrogate(seed=seed)
     t1 = time.perf_counter()
     loss = train(net, x, y, m, epochs=epochs, seed=seed, log=log)
     t_train = time.perf_counter() - t1
-    return net, {"curves": int(train_batches * train_count), "rows": int(len(y)),
+    return net, {"curves": int(len(y) // len(spec.times())), "rows": int(len(y)),
                  "site_updates": train_su, "data_s": t_data, "train_s": t_train,
                  "final_loss": loss}
 
 
 def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print, runner=None,
-                 predictor=None):
+                 predictor=None, domain=None):
     """Plain and surrogate-guided searches for every d, all driven in
     lockstep (one batched GPU run per round), each with its own ledger and
-    cache: no run is shared between searches. Returns one record per d."""
+    cache: no run is shared between searches. `domain` is the network's
+    training p range. Returns one record per d."""
     import time
 
     predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
     hi = len(grid) - 1
     searches = {}
     for d, k in zip(d_values, d_indices):
-        ys, cls = predictor(d, list(range(len(grid))))
+        ys, cls = restrict_to_domain(*predictor(d, list(range(len(grid)))), grid, domain)
         searches[("plain", k)] = (plain_steps(grid, 0, hi), d, k)
         searches[("surrogate", k)] = (surrogate_steps(ys, cls, grid, spec.times(), 0, hi), d, k)
     t0 = time.perf_counter()
@@ -439,19 +466,20 @@ def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print,
 
 def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int = 10,
             train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
-            epochs: int = 150, seed: int = 2013, log=print):
+            epochs: int = 150, seed: int = 2013, log=print, p_range=(0.04, 0.30)):
     """Train the surrogate on simulator curves, then search p_c for each d both
     ways. Returns a summary dict; training site updates are reported
     separately from the searches'."""
     spec = spec or RunSpec()
     grid = Grid(bits=bits)
     net, training = build_surrogate(d_values, spec, train_count, train_batches, train_L,
-                                    epochs, seed, log)
+                                    epochs, seed, log, p_range=p_range)
     out = {"spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps, "grid": len(grid),
                     "p_range": [float(grid.p[0]), float(grid.p[-1])]},
            "training": training, "searches": []}
     try:
-        out["searches"] = run_searches(net, d_values, range(len(d_values)), spec, grid, log)
+        out["searches"] = run_searches(net, d_values, range(len(d_values)), spec, grid, log,
+                                       domain=p_range)
     finally:
         net.close()
     return out
@@ -476,7 +504,11 @@ def main(argv=None):
     ap.add_argument("--save-net", type=str, default=None, help="write trained parameters (.npy)")
     ap.add_argument("--load-net", type=str, default=None, help="read parameters, skip training")
     ap.add_argument("--train-only", action="store_true")
-    ap.add_argument("--train-p", type=str, default="0.04,0.30", help="p range of the training curves")
+    ap.add_argument("--train-p", type=str, default="0.04,0.30",
+                    help="p range of the training curves, also the range where the network's "
+                         "predictions are trusted (give the loaded network's with --load-net)")
+    ap.add_argument("--train-data", type=str, default=None,
+                    help="training set cache (.npz): read if present, else simulated and written")
     ap.add_argument("--train-d", type=str, default=None,
                     help="d values of the training curves (default: the searched --d)")
     a = ap.parse_args(argv)
@@ -497,14 +529,14 @@ def main(argv=None):
         net, res["training"] = build_surrogate(
             train_d, spec, a.train_count, a.train_batches,
             tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log,
-            p_range=tuple(float(v) for v in a.train_p.split(",")))
+            p_range=tuple(float(v) for v in a.train_p.split(",")), data_path=a.train_data)
         print(json.dumps({"training": res["training"]}), flush=True)
     if a.save_net:
         np.save(a.save_net, net.params())
     if not a.train_only:
         keep = range(len(d_values)) if a.d_index is None else [int(v) for v in a.d_index.split(",")]
         res["searches"] = run_searches(net, [d_values[k] for k in keep], list(keep), spec, grid,
-                                       log)
+                                       log, domain=tuple(float(v) for v in a.train_p.split(",")))
     net.close()
     print(json.dumps(res), flush=True)
 

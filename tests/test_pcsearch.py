@@ -233,6 +233,40 @@ def test_spurious_low_predictions_do_not_move_the_flip():
     assert led.path[0][0] == F and led.runs <= 2
 
 
+def test_predictions_outside_the_training_range_are_not_trusted():
+    """A network that predicts 'active' again above its training p range
+    (where it extrapolates) would place its flip up there; restricted to its
+    training range it proposes its real flip first."""
+    grid = ps.Grid(bits=10)
+    F = 385
+
+    def pred(d, idx):
+        ys, cls = _family_predictor(F)(d, idx)
+        cls = cls.copy()
+        cls[990:1000] = False     # a spurious active island near the top end
+        return ys, cls
+    domain = (0.10, 0.22)
+    (lo, hi), led = ps.surrogate_bisect(None, 0.25, 0, grid, SPEC, runner=_family_runner(F),
+                                        predictor=pred, domain=domain)
+    assert (lo, hi) == (F - 1, F)
+    assert led.path[0][0] == F and led.runs <= 2
+    (lo2, hi2), led2 = ps.surrogate_bisect(None, 0.25, 0, grid, SPEC, runner=_family_runner(F),
+                                           predictor=pred)
+    assert (lo2, hi2) == (F - 1, F) and led2.path[0][0] >= 1000
+
+
+def test_domain_clamps_classes_and_hides_curves():
+    grid = ps.Grid(bits=4)
+    ys = np.zeros((len(grid), 3))
+    cls = np.array([True, False] * 8)
+    y2, c2 = ps.restrict_to_domain(ys, cls, grid, (0.1, 0.2))
+    out = (grid.p < 0.1) | (grid.p > 0.2)
+    assert not c2[grid.p < 0.1].any() and c2[grid.p > 0.2].all()
+    assert (c2[~out] == cls[~out]).all()
+    assert np.isinf(y2[out]).all() and (y2[~out] == 0).all()
+    assert ps.match_index(y2, np.zeros(3), np.ones(3, bool)) in np.nonzero(~out)[0]
+
+
 def test_two_sided_proposals_stay_in_the_middle_half():
     """Once both ends are simulated, proposals near an end of the bracket are
     replaced by midpoints, so a badly calibrated surrogate costs at most a
