@@ -30,10 +30,17 @@ DELTA_FLOOR = 0.05
 DELTA_HIGH = 0.35
 
 
+# p enters the surrogate centred and scaled: one cell of the 2^10-point search
+# grid then moves the input by 0.004, which is the resolution of the bfloat16
+# activations of the network's hidden products. Scaled as p / 0.25, a cell moved
+# it by 0.001 and neighbouring cells got identical predictions.
+P_MID, P_SCALE = 0.16, 0.07
+
+
 def features(p, d, t):
-    """Surrogate inputs (p / 0.25, d, log10(t) / 6), float32 [..., 3]."""
+    """Surrogate inputs ((p - P_MID) / P_SCALE, d, log10(t) / 6), float32 [..., 3]."""
     p, d, t = np.broadcast_arrays(np.asarray(p, float), np.asarray(d, float), np.asarray(t, float))
-    return np.stack([p / 0.25, d, np.log10(t) / 6.0], axis=-1).astype(np.float32)
+    return np.stack([(p - P_MID) / P_SCALE, d, np.log10(t) / 6.0], axis=-1).astype(np.float32)
 
 
 def _slope(logt, logr):
@@ -295,8 +302,20 @@ def plain_bisect(d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
     return res["plain"]
 
 
+def predicted_class(times, log10_rho) -> bool:
+    """Class of a surrogate curve for placing probes: inactive when its
+    delta_eff over the last half-decade exceeds DELTA_HIGH. The network
+    reproduces the level of delta_eff near p_c (about 0.2 at p_c, 1/2 for
+    decaying runs) better than the change of delta_eff between half-decades,
+    on which classify() also relies; simulated runs are classified by
+    classify()."""
+    r = 10.0 ** np.asarray(log10_rho, float)
+    return bool(delta_eff_windows(times, r)[1] > DELTA_HIGH)
+
+
 def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
-    """Surrogate curves log10 rho(p_j, d, t_k) and their classes for grid indices idx."""
+    """Surrogate curves log10 rho(p_j, d, t_k) and their classes
+    (predicted_class) for grid indices idx."""
     import torch
 
     times = np.asarray(spec.times(), float)
@@ -304,7 +323,7 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
     T = np.tile(times, len(idx))
     x = torch.from_numpy(features(P, d, T)).cuda()
     y = net.predict(x).cpu().numpy().astype(np.float64).reshape(len(idx), len(times))
-    cls = [classify(times, 10.0 ** y[k]) for k in range(len(idx))]
+    cls = [predicted_class(times, y[k]) for k in range(len(idx))]
     return y, np.array(cls, dtype=bool)
 
 
@@ -339,6 +358,14 @@ def training_batch(count: int, spec: RunSpec, seed: int, d_values=(0.1, 0.5, 0.9
     return insts
 
 
+def training_rows(insts, times):
+    """(p, d, t) of every row of simulate_training_set, in its order."""
+    P = np.array([i.p for i in insts], float)[None, :].repeat(len(times), 0)
+    D = np.array([i.d for i in insts], float)[None, :].repeat(len(times), 0)
+    T = np.asarray(times, float)[:, None].repeat(len(insts), 1)
+    return P.ravel(), D.ravel(), T.ravel()
+
+
 def simulate_training_set(insts, spec: RunSpec, seed: int, graph: bool = True):
     """One batched GPU run of all instances (one plane each) with records at
     spec.times(); returns (features [n,3], log10 rho [n], mask [n], site updates)."""
@@ -351,10 +378,7 @@ def simulate_training_set(insts, spec: RunSpec, seed: int, graph: bool = True):
     N = c[:, :, 0, 0].astype(np.float64)                       # [times, inst]
     L = np.array([i.L for i in insts], float)
     rho = N / (64.0 * L[None, :])
-    P = np.array([i.p for i in insts], float)[None, :].repeat(len(times), 0)
-    D = np.array([i.d for i in insts], float)[None, :].repeat(len(times), 0)
-    T = np.asarray(times, float)[:, None].repeat(len(insts), 1)
-    x = features(P.ravel(), D.ravel(), T.ravel())
+    x = features(*training_rows(insts, times))
     mask = (rho.ravel() > 0).astype(np.float32)
     y = np.log10(np.where(rho.ravel() > 0, rho.ravel(), 1.0)).astype(np.float32)
     su = int(sum(64 * i.L for i in insts) * spec.steps)
@@ -403,21 +427,24 @@ def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
     t0 = time.perf_counter()
     if data_path and os.path.exists(data_path):
         with np.load(data_path) as z:
-            x, y, m, train_su = z["x"], z["y"], z["m"], int(z["site_updates"])
+            x = features(z["p"], z["d"], z["t"])
+            y, m, train_su = z["y"], z["m"], int(z["site_updates"])
         log(f"training set read from {data_path}: {len(y)} rows")
     else:
-        xs, ys, ms, train_su = [], [], [], 0
+        raws, ys, ms, train_su = [], [], [], 0
         for b in range(train_batches):
             insts = training_batch(train_count, spec, seed + b, d_values=d_values,
                                    L_range=train_L, p_range=p_range)
-            x, y, m, su = simulate_training_set(insts, spec, seed + b)
-            xs.append(x), ys.append(y), ms.append(m)
+            _, y, m, su = simulate_training_set(insts, spec, seed + b)
+            raws.append(training_rows(insts, spec.times())), ys.append(y), ms.append(m)
             train_su += su
             log(f"training batch {b + 1}/{train_batches}: {len(insts)} curves, "
                 f"{time.perf_counter() - t0:.1f} s")
-        x, y, m = np.concatenate(xs), np.concatenate(ys), np.concatenate(ms)
+        P, D, T = (np.concatenate([r[k] for r in raws]) for k in range(3))
+        y, m = np.concatenate(ys), np.concatenate(ms)
+        x = features(P, D, T)
         if data_path:
-            np.savez(data_path, x=x, y=y, m=m, site_updates=np.int64(train_su))
+            np.savez(data_path, p=P, d=D, t=T, y=y, m=m, site_updates=np.int64(train_su))
     t_data = time.perf_counter() - t0
     net = pcpd.Surrogate(seed=seed)
     t1 = time.perf_counter()

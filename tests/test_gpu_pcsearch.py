@@ -63,7 +63,7 @@ def test_training_rows_are_the_oracle_rows(ps):
     live = rho > 0
     np.testing.assert_allclose(y[live], np.log10(rho[live]).astype(np.float32), rtol=0, atol=1e-6)
     P = np.repeat(np.array([[i.p for i in insts]]), len(times), 0).ravel()
-    np.testing.assert_allclose(x[:, 0], P / 0.25, rtol=1e-6)
+    np.testing.assert_allclose(x[:, 0], (P - ps.P_MID) / ps.P_SCALE, rtol=1e-5, atol=1e-6)
 
 
 def _valid_bracket(br, cls, n):

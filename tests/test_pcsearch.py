@@ -177,9 +177,33 @@ def test_match_index_finds_the_nearest_curve():
         assert ps.match_index(ys, ys[k] + 1e-4, late) == k
 
 
+def test_predicted_class_uses_the_level_of_delta_eff():
+    """A slowly steepening power law near delta = 0.2 is inactive for the
+    simulation's classifier (delta rises between half-decades) but not for
+    probe placement; a decay with delta near 1/2 is inactive for both."""
+    t = TIMES
+    steepening = 0.8 * t ** -0.2 * np.exp(-(t / 3e7) ** 0.5)
+    d_prev, d_last = ps.delta_eff_windows(t, steepening)
+    assert d_last > d_prev > 0.05 and d_last < ps.DELTA_HIGH
+    assert ps.classify(t, steepening)
+    assert not ps.predicted_class(t, np.log10(steepening))
+    decaying = 0.5 * t ** -0.5
+    assert ps.classify(t, decaying) and ps.predicted_class(t, np.log10(decaying))
+    flat = np.full_like(t, 0.3)
+    assert not ps.classify(t, flat) and not ps.predicted_class(t, np.log10(flat))
+
+
 def test_features():
-    x = ps.features([0.25, 0.125], [0.5, 0.1], [1.0, 1e6])
-    np.testing.assert_allclose(x, [[1.0, 0.5, 0.0], [0.5, 0.1, 1.0]], rtol=1e-6)
+    x = ps.features([0.23, 0.125], [0.5, 0.1], [1.0, 1e6])
+    np.testing.assert_allclose(x, [[1.0, 0.5, 0.0], [-0.5, 0.1, 1.0]], rtol=1e-5, atol=1e-6)
+
+
+def test_training_rows_follow_the_simulated_layout():
+    insts = [workloads.Instance(0.1, 0.5, 64, 0), workloads.Instance(0.2, 0.9, 128, 1)]
+    P, D, T = ps.training_rows(insts, [1, 10, 100])
+    np.testing.assert_array_equal(P, [0.1, 0.2] * 3)
+    np.testing.assert_array_equal(D, [0.5, 0.9] * 3)
+    np.testing.assert_array_equal(T, [1, 1, 10, 10, 100, 100])
 
 
 def test_lockstep_searches_match_the_sequential_ones():
