@@ -242,9 +242,9 @@ __device__ __forceinline__ bool windows_disjoint(uint32_t oa, uint32_t ob, uint3
 // between two barriers; otherwise team 0 applies its substep in one interval
 // and team 1 in the next. Each team then draws the masks of its next
 // substep between the loads and the arithmetic of its update, which fills
-// the LDS latency. The two teams run
-// their own loops (no register copies between the branches) and pass the
-// same number of barriers. Draws past the phase end are computed and dropped.
+// the LDS latency. The two teams run their own loops (no register copies
+// between the branches) and pass the same number of barriers. Draws past
+// the phase end are computed and dropped.
 // Each wavefront draws the local sites of 64 substeps at a time, one per
 // lane, and reads them back with v_readlane.
 // Window rows o-1 .. o+N lie inside the lane's own column when
