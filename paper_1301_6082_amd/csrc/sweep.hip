@@ -479,15 +479,21 @@ __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
     }
 }
 
+// LDS row pitch of the default tile (128 columns plus three spare, odd).
+constexpr uint32_t kDefaultPitch = 131;
+
 // One workgroup per tile, two lanes per block (the two teams). At most two
 // wavefronts per SIMD: with 128-block tiles two workgroups share a CU, with
-// 256-block tiles one does.
-template <int N>
+// 256-block tiles one does. PITCH is the LDS row pitch as a compile-time
+// constant (0: the ldw_arg argument); with a constant pitch the rows of a
+// window are immediate offsets from one address.
+template <int N, uint32_t PITCH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
           const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
-          uint32_t cols, uint32_t ldw) {
+          uint32_t cols, uint32_t ldw_arg) {
+    const uint32_t ldw = PITCH ? PITCH : ldw_arg;
     // first substep of the phase: the context's device clock plus this
     // launch's offset, so that a captured sequence of launches is valid at
     // any starting time
@@ -592,23 +598,38 @@ __global__ void zero_counts(Counts *__restrict__ out, uint32_t nlat) {
     }
 }
 
-template <int N>
-hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
-                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
-                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
-                          hipStream_t stream) {
+template <int N, uint32_t PITCH>
+hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                         const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                         uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                         hipStream_t stream) {
     const size_t lds = phase_lds_bytes(B, sh.ldw, S);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(kMaxLdsBytes));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(brs_phase<N>, dim3(ntiles), dim3(sh.threads), lds, stream, src, dst, lats,
-                       tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
+    hipLaunchKernelGGL((brs_phase<N, PITCH>), dim3(ntiles), dim3(sh.threads), lds, stream, src,
+                       dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
     return hipGetLastError();
+}
+
+// The default PCPD tile runs a copy of the kernel compiled for its pitch;
+// every other model and shape takes the pitch as an argument.
+template <int N>
+hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                          hipStream_t stream) {
+    if constexpr (N == 2) {
+        if (sh.ldw == kDefaultPitch)
+            return launch_kernel<N, kDefaultPitch>(src, dst, lats, tiles, ntiles, clock, s_off, S,
+                                                   B, sh, stream);
+    }
+    return launch_kernel<N, 0>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
 }
 
 }  // namespace
