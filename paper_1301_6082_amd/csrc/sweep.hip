@@ -386,7 +386,10 @@ __device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restr
 
 // load_tile for an even B and a 16-byte aligned ring: lane i handles the
 // site pairs (2i, 2i+1), (2i+2*nthr, ...), ..., so a tile of up to
-// 2*kCopyBatch*nthr words arrives in one round trip.
+// 2*kCopyBatch*nthr words arrives in one round trip. FIXED_ROW: 2*nthr is a
+// multiple of B, so every pair of a lane lies in the same row (the default
+// shapes); the row-wrap test then drops out of the loop.
+template <bool FIXED_ROW>
 __device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *__restrict__ ring,
                                                 uint32_t kfirst, uint32_t nb, uint32_t total,
                                                 uint32_t B, uint32_t ldw, uint32_t tid,
@@ -405,12 +408,14 @@ __device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *_
             a[u] = o * ldw + c;
             if (i0 + u * step < total) v[u] = rp[static_cast<uint64_t>(kg) * half + (o >> 1)];
             c += cstep;
-            o += ostep;
             kg += kstep;
-            if (o >= B) {
-                o -= B;
-                ++c;
-                ++kg;
+            if constexpr (!FIXED_ROW) {
+                o += ostep;
+                if (o >= B) {
+                    o -= B;
+                    ++c;
+                    ++kg;
+                }
             }
             if (kg >= nb) kg -= nb;
         }
@@ -449,7 +454,8 @@ __device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const
 }
 
 // store_interior for an even B and a 16-byte aligned destination, one site
-// pair per lane and access.
+// pair per lane and access; FIXED_ROW as for load_tile_pairs.
+template <bool FIXED_ROW>
 __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
                                                      const uint64_t *lds, uint32_t hb,
                                                      uint32_t total, uint32_t B, uint32_t ldw,
@@ -467,10 +473,12 @@ __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
                 v[u].b = lds[(o + 1u) * ldw + hb + c];
             }
             c += cstep;
-            o += ostep;
-            if (o >= B) {
-                o -= B;
-                ++c;
+            if constexpr (!FIXED_ROW) {
+                o += ostep;
+                if (o >= B) {
+                    o -= B;
+                    ++c;
+                }
             }
         }
 #pragma unroll
@@ -515,8 +523,11 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
                        ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0u;
 
     // ---- load tile + halo: consecutive lanes read consecutive words
-    if (pairs)
-        load_tile_pairs(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    const bool fixed_row = (2u * nthr) % B == 0u;
+    if (pairs && fixed_row)
+        load_tile_pairs<true>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    else if (pairs)
+        load_tile_pairs<false>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     else
         load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     __syncthreads();
@@ -542,8 +553,10 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
 
     // ---- write the interior back; it is contiguous in the ring
     uint64_t *out = dst + ld.base + static_cast<uint64_t>(td.k0) * B;
-    if (pairs)
-        store_interior_pairs(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+    if (pairs && fixed_row)
+        store_interior_pairs<true>(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+    else if (pairs)
+        store_interior_pairs<false>(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
     else
         store_interior(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
 }
