@@ -10,7 +10,8 @@ activations, the loss and its gradient stay unrounded. `bf16=False` drops the
 rounding, which makes the network an ordinary float64 network that the tests
 compare with PyTorch and with finite differences.
 
-Inputs of a row: (p / 0.25, d, log10(t) / 6); target: log10(rho).
+Inputs of a row: ((p - 0.16) / 0.07, d, log10(t) / 6), as the p_c search feeds
+them; target: log10(rho).
 
 Parameter vector (float32 master copy on the GPU), in this order:
     W1 [128][3], b1 [128], W2 [128][128], b2 [128], W3 [128][128], b3 [128],
@@ -132,6 +133,45 @@ def loss_and_grad(theta, x, target, mask=None, bf=True):
     return loss, pack(g)
 
 
+def forward_scale(theta, x):
+    """Per row, the sum of the magnitudes of the terms the output adds up:
+    sum_j |bf(h3_j) bf(w4_j)| + |b4|. Reordering or rounding the accumulation
+    moves y by a small multiple of this scale; a changed rounding point of an
+    operand moves it by about 2^-9 of it."""
+    _, c = forward(theta, x)
+    P, r = c["P"], c["r"]
+    return np.abs(r(c["h3"])) @ np.abs(r(P["w4"])) + abs(P["b4"][0])
+
+
+def grad_scale(theta, x, target, mask=None):
+    """Per parameter, the sum of the magnitudes of the terms its gradient adds
+    up, with the same operands and rounding points as loss_and_grad (for a
+    weight |bf(dz)|^T |bf(h)|, for a bias sum_r |dz_r|). Element-wise
+    tolerances of the GPU gradient are stated relative to this scale."""
+    y, c = forward(theta, x)
+    t = np.asarray(target, dtype=np.float64)
+    m = np.ones_like(t) if mask is None else np.asarray(mask, dtype=np.float64)
+    M = m.sum()
+    if M == 0:
+        return np.zeros(N_PARAMS)
+    P, r = c["P"], c["r"]
+    dy = 2.0 * (y - t) * m / M
+    a = np.abs
+    g = {}
+    g["w4"] = a(dy) @ a(r(c["h3"]))
+    g["b4"] = np.array([a(dy).sum()])
+    dz3 = np.outer(dy, r(P["w4"])) * gelu_grad(c["z3"])
+    g["W3"] = a(r(dz3)).T @ a(r(c["h2"]))
+    g["b3"] = a(dz3).sum(axis=0)
+    dz2 = (r(dz3) @ r(P["W3"])) * gelu_grad(c["z2"])
+    g["W2"] = a(r(dz2)).T @ a(r(c["h1"]))
+    g["b2"] = a(dz2).sum(axis=0)
+    dz1 = (r(dz2) @ r(P["W2"])) * gelu_grad(c["z1"])
+    g["W1"] = a(dz1).T @ a(c["xb"])
+    g["b1"] = a(dz1).sum(axis=0)
+    return pack(g)
+
+
 class Adam:
     """Adam (Kingma & Ba): m, v moments with bias correction."""
 
@@ -162,6 +202,6 @@ def init_params(seed):
 
 
 def features(p, d, t):
-    """Network inputs of (p, d, t): (p / 0.25, d, log10(t) / 6)."""
+    """Network inputs of (p, d, t): ((p - 0.16) / 0.07, d, log10(t) / 6)."""
     p, d, t = np.broadcast_arrays(np.asarray(p, float), np.asarray(d, float), np.asarray(t, float))
-    return np.stack([p / 0.25, d, np.log10(t) / 6.0], axis=-1)
+    return np.stack([(p - 0.16) / 0.07, d, np.log10(t) / 6.0], axis=-1)

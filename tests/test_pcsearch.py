@@ -198,6 +198,15 @@ def test_features():
     np.testing.assert_allclose(x, [[1.0, 0.5, 0.0], [-0.5, 0.1, 1.0]], rtol=1e-5, atol=1e-6)
 
 
+def test_search_feeds_the_inputs_the_surrogate_boundary_documents():
+    """The rows the search builds are the ones include/pcpd_mlp.h and the
+    network's oracle state: ((p - 0.16) / 0.07, d, log10(t) / 6)."""
+    from oracle import mlp_oracle as mo
+    rng = np.random.default_rng(3)
+    p, d, t = rng.uniform(0.02, 0.3, 50), rng.choice([0.1, 0.5, 0.9], 50), 10 ** rng.uniform(0, 6, 50)
+    np.testing.assert_allclose(ps.features(p, d, t), mo.features(p, d, t), rtol=1e-6, atol=1e-6)
+
+
 def test_training_rows_follow_the_simulated_layout():
     insts = [workloads.Instance(0.1, 0.5, 64, 0), workloads.Instance(0.2, 0.9, 128, 1)]
     P, D, T = ps.training_rows(insts, [1, 10, 100])
