@@ -116,27 +116,51 @@ typedef struct {
 typedef struct pcpd_ctx pcpd_ctx;
 
 /* Bytes of device memory for the two lattice copies of these instances
- * (2 * 8 * planes * sum L). Validates like pcpd_init. */
+ * (2 * 8 * planes * sum L): one word per site holding 64 samples (paper
+ * Sec. 4, classical multispin). Validates like pcpd_init; *bytes_out is
+ * written only on success. */
 PCPD_API int pcpd_lattice_bytes(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
                        size_t *bytes_out);
 
-/* Create a context at Monte Carlo step t0 (t0 > 0 resumes a stored lattice:
- * the lattice and t fully determine the future). Validation failures return
- * PCPD_EINVAL before any device work and leave *out untouched. */
+/* Create a context of n_inst instances of the model of paper eq. (1) (rates
+ * p, d; ring length L, Sec. 2), each started full, empty or from host words,
+ * at Monte Carlo step t0. t0 > 0 resumes a stored lattice: the lattice and t
+ * fully determine the future, since every random number is addressed by
+ * (seed, stream_id, plane, block, substep). t0 is shared by all instances of
+ * a context; instances at different times go in separate contexts.
+ * Ownership: *out is library-owned until pcpd_free; cfg, inst and the host
+ * words are read during the call only; dev->dev_buf (if given) is borrowed
+ * for the context's lifetime. Validation failures return PCPD_EINVAL (or
+ * PCPD_EOVERFLOW if t0 * B leaves 64 bits) before any device work and leave
+ * *out untouched; a failed allocation returns PCPD_ENOMEM. */
 PCPD_API int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
               uint32_t n_inst, uint64_t t0, const pcpd_device *dev);
 
-/* Advance every instance by n_steps Monte Carlo steps (n_steps * B substeps).
- * Asynchronous. PCPD_EOVERFLOW if (t + n_steps) * B leaves 64 bits. */
+/* Advance every instance by n_steps Monte Carlo steps: paper Algorithm 1
+ * (one attempt maps time t to t + 1/L) applied in the shared-local-site order
+ * of Sec. 3 (every block of B sites attempted at one drawn local site per
+ * substep, B substeps per step), all 64 samples of a word at once with the
+ * bit masks of Sec. 4 (Algorithm 2, read so that annihilation clears the
+ * tuple, l AND NOT mask, and low fission sets site j-1 itself, as Algorithm 1
+ * and the prose of Sec. 4.3 state).
+ * Asynchronous: errors of the enqueued kernels surface at the next
+ * synchronising call. PCPD_EOVERFLOW if (t + n_steps) * B leaves 64 bits;
+ * n_steps = 0 does nothing. */
 PCPD_API int pcpd_sweep(pcpd_ctx *ctx, uint64_t n_steps);
 
-/* Counts of the current lattice into out[n_inst * planes] (instance-major).
- * Synchronises. */
+/* The order parameter of paper Sec. 1 and the pair density of Sec. 5.3 for
+ * the current lattice: out[i * planes + q] = (N, N_pair, alive) of instance
+ * i, plane q (rho = N / (64 L)). `out` is a host array of n_inst * planes
+ * entries, written only on success. Synchronises. */
 PCPD_API int pcpd_density(pcpd_ctx *ctx, pcpd_counts *out);
 
-/* Sweep to each of the strictly increasing times[0..n_times) (each >= the
- * current t) and record the counts there: out[r * n_inst * planes + i * planes + q].
- * Synchronises once at the end. */
+/* Density series at scheduled times, as analysed in paper Sec. 5.3: sweep
+ * (as pcpd_sweep) to each of the strictly increasing times[0..n_times) (each
+ * >= the current t; a time equal to t records the current lattice) and record
+ * the counts there into the host array
+ * out[r * n_inst * planes + i * planes + q]. PCPD_EINVAL for unordered times
+ * or a time before t (nothing is enqueued then). Synchronises once at the
+ * end. */
 PCPD_API int pcpd_run(pcpd_ctx *ctx, const uint64_t *times, uint32_t n_times, pcpd_counts *out);
 
 /* Copy instance `inst`'s planes*L words (plane-major, natural order) to or

@@ -6,8 +6,10 @@
  * for the critical annihilation rate p_c of paper Sec. 2 (active phase for
  * p < p_c, inactive for p > p_c; p_c depends on d).
  *
- * Network: inputs (p / 0.25, d, log10(t) / 6); layers 3 -> 128 -> 128 -> 128
- * -> 1 with tanh-form GELU after each hidden layer; output log10(rho).
+ * Network: three inputs per row; the p_c search feeds ((p - 0.16) / 0.07, d,
+ * log10(t) / 6), which puts one cell of its p grid above the bfloat16
+ * resolution of the first products. Layers 3 -> 128 -> 128 -> 128 -> 1 with
+ * tanh-form GELU after each hidden layer; output log10(rho).
  * Parameters: one float32 vector of PCPD_MLP_PARAMS values, in the order
  *   W1[128][3], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
  *   w4[128], b4[1]          (weights output-major, W[o][i]).
