@@ -144,10 +144,20 @@ def forward_scale(theta, x):
 
 
 def grad_scale(theta, x, target, mask=None):
-    """Per parameter, the sum of the magnitudes of the terms its gradient adds
-    up, with the same operands and rounding points as loss_and_grad (for a
-    weight |bf(dz)|^T |bf(h)|, for a bias sum_r |dz_r|). Element-wise
-    tolerances of the GPU gradient are stated relative to this scale."""
+    """Per parameter, the magnitude its gradient is computed from: the sum of
+    the magnitudes of every term that enters it, carried through the whole
+    backward chain. A dot product evaluated in floating point is off by a
+    small multiple of the unit roundoff times the sum of the magnitudes of its
+    terms, not of its value; when an upstream sum such as dh1 = bf(dz2) W2,
+    or the residual y - target, cancels, its absolute error is that of the
+    magnitudes, and it reaches every gradient computed from it. So the
+    magnitudes are propagated, starting from those of the residual:
+        Sy = 2 m / M (sum_j |bf(h3_j) bf(w4_j)| + |b4| + |target|),
+        S3 = Sy |bf(w4)| |gelu'(z3)|,  S2 = (S3 |bf(W3)|) |gelu'(z2)|,
+        S1 = (S2 |bf(W2)|) |gelu'(z1)|,
+    and a weight's scale is S_k^T |bf(h_{k-1})| (|bf(x)| for W1, |bf(h3)|
+    with Sy for w4), a bias's sum_r S_k. Element-wise tolerances of the GPU
+    gradient are stated relative to this scale."""
     y, c = forward(theta, x)
     t = np.asarray(target, dtype=np.float64)
     m = np.ones_like(t) if mask is None else np.asarray(mask, dtype=np.float64)
@@ -155,20 +165,20 @@ def grad_scale(theta, x, target, mask=None):
     if M == 0:
         return np.zeros(N_PARAMS)
     P, r = c["P"], c["r"]
-    dy = 2.0 * (y - t) * m / M
     a = np.abs
+    sy = 2.0 * m / M * (a(r(c["h3"])) @ a(r(P["w4"])) + abs(P["b4"][0]) + a(t))
     g = {}
-    g["w4"] = a(dy) @ a(r(c["h3"]))
-    g["b4"] = np.array([a(dy).sum()])
-    dz3 = np.outer(dy, r(P["w4"])) * gelu_grad(c["z3"])
-    g["W3"] = a(r(dz3)).T @ a(r(c["h2"]))
-    g["b3"] = a(dz3).sum(axis=0)
-    dz2 = (r(dz3) @ r(P["W3"])) * gelu_grad(c["z2"])
-    g["W2"] = a(r(dz2)).T @ a(r(c["h1"]))
-    g["b2"] = a(dz2).sum(axis=0)
-    dz1 = (r(dz2) @ r(P["W2"])) * gelu_grad(c["z1"])
-    g["W1"] = a(dz1).T @ a(c["xb"])
-    g["b1"] = a(dz1).sum(axis=0)
+    g["w4"] = sy @ a(r(c["h3"]))
+    g["b4"] = np.array([sy.sum()])
+    s3 = np.outer(sy, a(r(P["w4"]))) * a(gelu_grad(c["z3"]))
+    g["W3"] = s3.T @ a(r(c["h2"]))
+    g["b3"] = s3.sum(axis=0)
+    s2 = (s3 @ a(r(P["W3"]))) * a(gelu_grad(c["z2"]))
+    g["W2"] = s2.T @ a(r(c["h1"]))
+    g["b2"] = s2.sum(axis=0)
+    s1 = (s2 @ a(r(P["W2"]))) * a(gelu_grad(c["z1"]))
+    g["W1"] = s1.T @ a(c["xb"])
+    g["b1"] = s1.sum(axis=0)
     return pack(g)
 
 

@@ -57,28 +57,40 @@ def test_forward_matches_oracle(pcpd, n):
     assert worst <= FLIP
 
 
-# Element-wise bounds, relative to the per-element scale of the oracle (the sum
-# of the magnitudes of the terms the element adds up; mlp_oracle.grad_scale,
-# forward_scale): float32 accumulation of at most a few hundred partial sums
-# moves an element by well under EXACT of its scale; an element where one side
-# rounds an operand to the other neighbouring bfloat16 value (a tie decided by
-# the last float32 bit) moves by at most FLIP, and only a small share of the
-# elements may do so.
+# Element-wise bounds. Gradients are compared relative to mlp_oracle.grad_scale,
+# the magnitudes of all the terms an element is computed from, propagated
+# through the backward chain: float32 evaluation of a dot product is off by a
+# small multiple of the unit roundoff u = 2^-24 times the sum of the magnitudes
+# of its terms, and an upstream sum that cancels passes that absolute error on.
+# With rounding errors of random sign the multiple grows like the square root
+# of the number of terms summed (here up to max(n, 128)), so an element must
+# agree within exact_bound(n) = 8 sqrt(max(n, 128)) u of its scale. Where one
+# side rounds an operand to the other neighbouring bfloat16 value (a tie
+# decided by the last float32 bit), the elements that operand enters move by
+# at most FLIP of their scale. One such activation of one row enters a whole
+# row or column of a weight gradient (1/128 of its elements), so a handful of
+# them moves a few percent of the elements: at most FLIP_SHARE of the elements
+# (about six flipped activations) may lie beyond the exact bound. Forward
+# outputs use forward_scale and EXACT.
 EXACT = 2e-5
 FLIP = 2.0 ** -6
-FLIP_SHARE = 0.01
+FLIP_SHARE = 0.05
 
 
-def _elementwise(a, b, scale, tag):
-    """(share of elements beyond EXACT, largest relative error) of a vs b."""
+def exact_bound(n):
+    return 8.0 * np.sqrt(max(n, mo.H)) * 2.0 ** -24
+
+
+def _elementwise(a, b, scale, tag, bound=EXACT):
+    """(share of elements beyond `bound`, largest relative error) of a vs b."""
     rel = np.abs(a - b) / (scale + 1e-30)
-    share = float((rel > EXACT).mean())
+    share = float((rel > bound).mean())
     print(f"[mlp elem] {tag}: max rel {rel.max():.2e}, 99.9% {np.quantile(rel, 0.999):.2e}, "
-          f"share beyond {EXACT:g}: {share:.2e}", flush=True)
+          f"share beyond {bound:.2g}: {share:.2e}", flush=True)
     return share, float(rel.max())
 
 
-@pytest.mark.parametrize("n", [200, 777, 4096])
+@pytest.mark.parametrize("n", [128, 200, 777, 4096])
 def test_gradient_matches_oracle_elementwise(pcpd, n):
     theta = _theta(2)
     x, t, m = _data(n, 10 + n)
@@ -94,31 +106,35 @@ def test_gradient_matches_oracle_elementwise(pcpd, n):
     o = 0
     for name, shape in mo.SIZES:
         k = int(np.prod(shape))
-        share, worst = _elementwise(g[o:o + k], rg[o:o + k], scale[o:o + k], f"n={n} {name}")
+        share, worst = _elementwise(g[o:o + k], rg[o:o + k], scale[o:o + k], f"n={n} {name}",
+                                    exact_bound(n))
         assert share <= FLIP_SHARE, name
         assert worst <= FLIP, name
         o += k
 
 
-def _grad_unrounded_dz3(theta, x, t, m):
-    """The oracle's gradient with one rounding point moved: dz3 enters the
-    W3 products unrounded (a planted mistake, on the CPU)."""
+def _planted_grads(theta, x, t, m):
+    """The oracle's weight gradients with one rounding point moved per layer
+    (planted mistakes, on the CPU): dz3 enters the W3 product unrounded, dz2
+    the W2 product, x the W1 sums."""
     y, c = mo.forward(theta, x)
     P, r = c["P"], c["r"]
     dy = 2.0 * (y - t) * m / m.sum()
     dz3 = np.outer(dy, r(P["w4"])) * mo.gelu_grad(c["z3"])
     dW3 = dz3.T @ r(c["h2"])
-    dh2 = dz3 @ r(P["W3"])
-    dz2 = dh2 * mo.gelu_grad(c["z2"])
-    dW2 = r(dz2).T @ r(c["h1"])
-    return dW3.reshape(-1), dW2.reshape(-1)
+    dz2 = (r(dz3) @ r(P["W3"])) * mo.gelu_grad(c["z2"])
+    dW2 = dz2.T @ r(c["h1"])
+    dz1 = (r(dz2) @ r(P["W2"])) * mo.gelu_grad(c["z1"])
+    dW1 = dz1.T @ np.asarray(x, dtype=np.float64)
+    return {"W3": dW3.reshape(-1), "W2": dW2.reshape(-1), "W1": dW1.reshape(-1)}
 
 
 def test_elementwise_bound_catches_a_moved_rounding_point(pcpd):
     """The element-wise bound is tight enough to see a rounding point placed
-    differently: against an oracle that skips the bfloat16 rounding of dz3,
-    the GPU's weight gradients break it."""
-    n = 200
+    differently in any layer: against an oracle that skips one bfloat16
+    rounding (of dz3, of dz2 or of x), the GPU's gradient of that layer's
+    weights breaks it."""
+    n = 128
     theta = _theta(2)
     x, t, m = _data(n, 10 + n)
     x = x.astype(np.float32).astype(np.float64)
@@ -133,10 +149,9 @@ def test_elementwise_bound_catches_a_moved_rounding_point(pcpd):
     for name, shape in mo.SIZES:
         offs[name] = (o, o + int(np.prod(shape)))
         o = offs[name][1]
-    dW3, dW2 = _grad_unrounded_dz3(theta, x, t, m)
-    for name, planted in (("W3", dW3), ("W2", dW2)):
+    for name, planted in _planted_grads(theta, x, t, m).items():
         a, b = offs[name]
-        share, _ = _elementwise(g[a:b], planted, scale[a:b], f"planted {name}")
+        share, _ = _elementwise(g[a:b], planted, scale[a:b], f"planted {name}", exact_bound(n))
         assert share > FLIP_SHARE, name
 
 
@@ -150,12 +165,14 @@ def test_mask_all_zero_gives_zero_gradient(pcpd):
 
 
 def test_adam_steps_match_oracle(pcpd):
-    """Three Adam steps on both sides from the same start, compared element by
-    element. An Adam step moves a parameter by lr * mhat / (sqrt(vhat) + eps);
-    where the two gradients agree to EXACT of their scale the steps agree to a
-    small fraction of lr. Only parameters whose gradient is itself within a few
-    EXACT of zero (relative to its scale) may step differently, by at most
-    2 lr per step."""
+    """Three Adam steps, each checked element by element against the oracle's
+    Adam applied to the same gradient: the GPU's own gradient at the GPU's
+    current parameters (pcpd_mlp_grads runs the kernels of the training step
+    on the same rows, so it is that step's gradient). This isolates the
+    optimiser from the gradient, whose parity is tested above; what remains
+    is float32 against float64 arithmetic in the update (a few float32 ulps of
+    lr) and the rounding of the float32 master copy (half an ulp of the
+    parameter). The loss of each step is also compared with the oracle's."""
     theta = _theta(4)
     x, t, m = _data(512, 4)
     x = x.astype(np.float32).astype(np.float64)
@@ -164,26 +181,21 @@ def test_adam_steps_match_oracle(pcpd):
     net = pcpd.Surrogate(seed=0)
     net.set_params(theta)
     opt = mo.Adam(mo.N_PARAMS, lr=lr)
-    th = theta.copy()
     xs, ts, ms = _cuda(x), _cuda(t), _cuda(m)
-    tiny = np.zeros(mo.N_PARAMS, dtype=bool)   # gradient ~0 at this or an earlier step
+    before = net.params().astype(np.float64)
     for step in range(3):
+        _, g = net.grads(xs, ts, ms)
         loss = net.train_step(xs, ts, ms, lr=lr, want_loss=True)
-        rl, rg = mo.loss_and_grad(th, x, t, m)
-        scale = mo.grad_scale(th, x, t, m)
+        rl, _ = mo.loss_and_grad(before, x, t, m)
         assert abs(loss - rl) <= 1e-5 * max(1.0, rl), step
-        th = opt.step(th, rg)
-        gpu = net.params().astype(np.float64)
-        diff = np.abs(gpu - th)
-        # float32 master copy: a few float32 ulps of the parameter (one rounding per
-        # step) plus the step's own error
-        ok = diff <= 1e-3 * lr + 2.0 ** -21 * np.abs(th)
-        tiny |= np.abs(rg) <= 100 * EXACT * scale
-        print(f"[mlp adam] step {step}: {ok.mean():.6f} of parameters within 1e-3 lr; "
-              f"outside: {int((~ok).sum())}, of which gradient ~0: {int((~ok & tiny).sum())}; "
-              f"max diff {diff.max() / lr:.2e} lr", flush=True)
-        assert (ok | tiny).all(), step
-        assert diff.max() <= 2.0 * lr * (step + 1)
+        want = opt.step(before, g.astype(np.float64))
+        after = net.params().astype(np.float64)
+        diff = np.abs(after - want)
+        bound = 1e-5 * lr + 2.0 ** -24 * np.abs(want)
+        print(f"[mlp adam] step {step}: max |diff| {diff.max() / lr:.2e} lr, "
+              f"max diff/bound {(diff / bound).max():.3f}", flush=True)
+        assert (diff <= bound).all(), step
+        before = after
 
 
 def test_training_on_gpu_reduces_the_loss(pcpd):
