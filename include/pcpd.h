@@ -65,7 +65,8 @@ typedef enum {
     PCPD_ENOMEM = -2,     /* a device or host allocation failed */
     PCPD_EDEVICE = -3,    /* a HIP call or enqueued kernel failed */
     PCPD_ESTATE = -4,     /* the context is unusable after an earlier device error */
-    PCPD_EOVERFLOW = -5   /* the substep counter t*B would leave 64 bits */
+    PCPD_EOVERFLOW = -5,  /* the substep counter t*B would leave 64 bits */
+    PCPD_ELIMIT = -6      /* the problem exceeds the fixed workspace of pcpd_run_noalloc */
 } pcpd_status;
 
 typedef enum { PCPD_DP = 1, PCPD_PCPD = 2, PCPD_TCPD = 3, PCPD_QCPD = 4 } pcpd_model; /* = tuple size n */
@@ -206,6 +207,46 @@ PCPD_API int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen);
  * both. Enabling does not change results. */
 PCPD_API int pcpd_profile(pcpd_ctx *ctx, int enable);
 PCPD_API int pcpd_profile_read(pcpd_ctx *ctx, double *kernel_ms, uint64_t *launches);
+
+/* ---- Allocation-free run ------------------------------------------------
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation). The same
+ * computation as pcpd_init (start taken from device memory) followed by
+ * pcpd_run, with no context: the spare lattice copy, the ring and tile tables,
+ * the count records and the device clock live in one fixed workspace that the
+ * library holds per GPU (a device variable of about 35 MiB, kept until the
+ * process ends). The call allocates nothing, on the device or through any
+ * library routine.
+ *
+ * Limits (PCPD_ELIMIT beyond them, checked before any device work):
+ *   planes * sum L           <= PCPD_NOALLOC_MAX_WORDS  (2^22 words, 32 MiB)
+ *   n_inst * planes          <= PCPD_NOALLOC_MAX_RINGS
+ *   n_times * n_inst * planes <= PCPD_NOALLOC_MAX_RECORDS
+ *   (and at most 65536 tiles and 8192 density chunks, which the limits
+ *   above imply for B = 64).
+ *
+ * Arguments: cfg and inst as for pcpd_init, except that inst[i].init and
+ * host_words are ignored. dev_lattice: DEVICE memory of the current HIP
+ * device, planes * sum L uint64 words laid out as the context keeps them
+ * (instance-major, then plane-major, natural site order, 8-byte aligned),
+ * holding the lattice at Monte Carlo step t0 on entry and at
+ * times[n_times - 1] on return (unchanged if n_times == 0); borrowed for the
+ * call. times, n_times, out: as for pcpd_run (times >= t0, strictly
+ * increasing; out a host array of n_times * n_inst * planes records).
+ * hip_stream: the stream to run on (NULL = null stream), of the current
+ * device. Synchronous: returns after the records are on the host.
+ * Results are bit-identical to pcpd_init + pcpd_run on the same start.
+ * Errors: PCPD_EINVAL / PCPD_EOVERFLOW as pcpd_init and pcpd_run (nothing
+ * enqueued), PCPD_ELIMIT, PCPD_EDEVICE for a failed HIP call or kernel.
+ * All calls on one GPU share its workspace: calls that overlap in time on
+ * the same GPU (two host threads, or streams of one device) race and give
+ * undefined results; calls made one after another are independent. */
+#define PCPD_NOALLOC_MAX_WORDS (1ull << 22)
+#define PCPD_NOALLOC_MAX_RINGS 4096u
+#define PCPD_NOALLOC_MAX_RECORDS 65536u
+PCPD_API int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+                              uint64_t t0, uint64_t *dev_lattice, const uint64_t *times,
+                              uint32_t n_times, pcpd_counts *out, void *hip_stream);
 
 /* Release the context and everything the library allocated for it. */
 PCPD_API int pcpd_free(pcpd_ctx *ctx);

@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -94,7 +95,10 @@ uint64_t rate_threshold(double q) { return static_cast<uint64_t>(std::rint(std::
 
 bool rate_ok(double q) { return std::isfinite(q) && q >= 0.0 && q <= 1.0; }
 
-int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst) {
+// check_init: also check the start kind and its host words (pcpd_init);
+// pcpd_run_noalloc takes its start from device memory and ignores them.
+int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+             bool check_init = true) {
     if (!cfg || !inst || n_inst == 0) return PCPD_EINVAL;
     if (cfg->model < 1 || cfg->model > 4) return PCPD_EINVAL;
     const uint32_t n = static_cast<uint32_t>(cfg->model);
@@ -105,8 +109,8 @@ int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst)
         if (!rate_ok(in.p) || !rate_ok(in.d)) return PCPD_EINVAL;
         if (in.L < cfg->B || in.L % cfg->B != 0) return PCPD_EINVAL;
         if (in.L / cfg->B >= (1ull << 32)) return PCPD_EINVAL;
-        if (in.init < PCPD_INIT_FULL || in.init > PCPD_INIT_HOST) return PCPD_EINVAL;
-        if (in.init == PCPD_INIT_HOST && !in.host_words) return PCPD_EINVAL;
+        if (check_init && (in.init < PCPD_INIT_FULL || in.init > PCPD_INIT_HOST)) return PCPD_EINVAL;
+        if (check_init && in.init == PCPD_INIT_HOST && !in.host_words) return PCPD_EINVAL;
         const uint64_t words = in.L * cfg->planes;
         if (words / cfg->planes != in.L || total + words < total) return PCPD_EINVAL;
         total += words;
@@ -162,12 +166,13 @@ int fail(pcpd_ctx *ctx, hipError_t e) {
 
 void drop_graphs(pcpd_ctx *ctx);
 
-hipError_t build_tiles(pcpd_ctx *ctx) {
-    drop_graphs(ctx);  // captured launches refer to the old tile table
+// Tiles of a shape over a set of rings: each ring cut into runs of at most
+// cols - 2*hb interior blocks.
+std::vector<TileDesc> plan_tiles(const std::vector<LatDesc> &lats, const PhaseShape &shape) {
     std::vector<TileDesc> tiles;
-    const uint32_t kmax = ctx->shape.cols - 2 * ctx->shape.hb;
-    for (uint32_t l = 0; l < ctx->nlat; ++l) {
-        const uint32_t nb = ctx->lats[l].nblocks;
+    const uint32_t kmax = shape.cols - 2 * shape.hb;
+    for (uint32_t l = 0; l < lats.size(); ++l) {
+        const uint32_t nb = lats[l].nblocks;
         for (uint32_t k0 = 0; k0 < nb; k0 += kmax) {
             TileDesc td{};
             td.lat = l;
@@ -176,6 +181,55 @@ hipError_t build_tiles(pcpd_ctx *ctx) {
             tiles.push_back(td);
         }
     }
+    return tiles;
+}
+
+// Chunks of the density reduction: every ring cut into runs of kDenChunkWords.
+std::vector<DenChunk> plan_chunks(const std::vector<LatDesc> &lats) {
+    std::vector<DenChunk> chunks;
+    for (uint32_t l = 0; l < lats.size(); ++l) {
+        for (uint64_t w0 = 0; w0 < lats[l].L; w0 += kDenChunkWords) {
+            DenChunk c{};
+            c.lat = l;
+            c.w0 = w0;
+            c.nw = static_cast<uint32_t>(std::min<uint64_t>(kDenChunkWords, lats[l].L - w0));
+            chunks.push_back(c);
+        }
+    }
+    return chunks;
+}
+
+// Ring descriptors of validated instances, instance-major then plane-major,
+// concatenated from word 0; *total_words receives planes * sum L.
+std::vector<LatDesc> plan_lats(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+                               uint64_t *total_words) {
+    std::vector<LatDesc> lats;
+    uint64_t base = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const uint64_t kd = rate_threshold(inst[i].d), kp = rate_threshold(inst[i].p);
+        for (uint32_t q = 0; q < cfg->planes; ++q) {
+            LatDesc ld{};
+            ld.base = base + q * inst[i].L;
+            ld.L = inst[i].L;
+            ld.nblocks = static_cast<uint32_t>(inst[i].L / cfg->B);
+            ld.plane = q;
+            ld.key0 = cfg->seed;
+            ld.key1 = inst[i].stream_id;
+            ld.kd_hi = static_cast<uint32_t>(kd >> 32);
+            ld.kd_lo = static_cast<uint32_t>(kd);
+            ld.kp_hi = static_cast<uint32_t>(kp >> 32);
+            ld.kp_lo = static_cast<uint32_t>(kp);
+            lats.push_back(ld);
+        }
+        base += inst[i].L * cfg->planes;
+    }
+    *total_words = base;
+    return lats;
+}
+
+hipError_t build_tiles(pcpd_ctx *ctx) {
+    drop_graphs(ctx);  // captured launches refer to the old tile table
+    const std::vector<TileDesc> tiles = plan_tiles(ctx->lats, ctx->shape);
     if (ctx->d_tiles) {
         hipError_t e = hipFree(ctx->d_tiles);
         ctx->d_tiles = nullptr;
@@ -470,6 +524,56 @@ hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t
     return e;
 }
 
+// ---- workspace of pcpd_run_noalloc -------------------------------------
+//
+// One fixed region per device, in the code object's data: the spare lattice
+// copy the phases alternate with, the ring, tile and density-chunk tables,
+// the count records and the device clock. Each region starts 256-byte aligned.
+constexpr uint64_t kNaWords = PCPD_NOALLOC_MAX_WORDS;
+constexpr uint64_t kNaRings = PCPD_NOALLOC_MAX_RINGS;
+constexpr uint64_t kNaRecords = PCPD_NOALLOC_MAX_RECORDS;
+constexpr uint64_t kNaTiles = 65536;
+constexpr uint64_t kNaChunks = 8192;
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kNaOffLats = align256(kNaWords * sizeof(uint64_t));
+constexpr size_t kNaOffTiles = kNaOffLats + align256(kNaRings * sizeof(LatDesc));
+constexpr size_t kNaOffChunks = kNaOffTiles + align256(kNaTiles * sizeof(TileDesc));
+constexpr size_t kNaOffCounts = kNaOffChunks + align256(kNaChunks * sizeof(DenChunk));
+constexpr size_t kNaOffClock = kNaOffCounts + align256(kNaRecords * sizeof(Counts));
+constexpr size_t kNaBytes = kNaOffClock + 256;
+
+}  // namespace
+
+// The workspace itself. In host code this name stands for the variable but is
+// not its device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (noalloc_workspace).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex na_mu;
+unsigned char *na_ptr[kNaMaxDevices] = {};
+
+// Device address of the current device's copy of the workspace, looked up on
+// the first call on that device (with it current) and kept.
+hipError_t noalloc_workspace(unsigned char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(na_mu);
+    if (!na_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        na_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = na_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -515,28 +619,11 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
     ctx->phase_max = pmax;
     ctx->stream = dev ? static_cast<hipStream_t>(dev->hip_stream) : nullptr;
 
-    uint64_t base = 0;
+    ctx->lats = plan_lats(cfg, inst, n_inst, &ctx->total_words);
     for (uint32_t i = 0; i < n_inst; ++i) {
         ctx->L.push_back(inst[i].L);
-        ctx->inst_base.push_back(base);
-        const uint64_t kd = rate_threshold(inst[i].d), kp = rate_threshold(inst[i].p);
-        for (uint32_t q = 0; q < cfg->planes; ++q) {
-            LatDesc ld{};
-            ld.base = base + q * inst[i].L;
-            ld.L = inst[i].L;
-            ld.nblocks = static_cast<uint32_t>(inst[i].L / cfg->B);
-            ld.plane = q;
-            ld.key0 = cfg->seed;
-            ld.key1 = inst[i].stream_id;
-            ld.kd_hi = static_cast<uint32_t>(kd >> 32);
-            ld.kd_lo = static_cast<uint32_t>(kd);
-            ld.kp_hi = static_cast<uint32_t>(kp >> 32);
-            ld.kp_lo = static_cast<uint32_t>(kp);
-            ctx->lats.push_back(ld);
-        }
-        base += inst[i].L * cfg->planes;
+        ctx->inst_base.push_back(ctx->lats[i * cfg->planes].base);
     }
-    ctx->total_words = base;
 
     hipError_t e = hipSuccess;
     if (dev && dev->dev_buf) {
@@ -554,17 +641,7 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
     }
     ctx->buf[1] = ctx->buf[0] + ctx->total_words;
 
-    // density chunks
-    std::vector<DenChunk> chunks;
-    for (uint32_t l = 0; l < ctx->nlat; ++l) {
-        for (uint64_t w0 = 0; w0 < ctx->lats[l].L; w0 += kDenChunkWords) {
-            DenChunk c{};
-            c.lat = l;
-            c.w0 = w0;
-            c.nw = static_cast<uint32_t>(std::min<uint64_t>(kDenChunkWords, ctx->lats[l].L - w0));
-            chunks.push_back(c);
-        }
-    }
+    const std::vector<DenChunk> chunks = plan_chunks(ctx->lats);
     ctx->nchunks = static_cast<uint32_t>(chunks.size());
 
     if ((e = hipMalloc(&ctx->d_lats, ctx->lats.size() * sizeof(LatDesc))) != hipSuccess ||
@@ -781,6 +858,93 @@ int pcpd_free(pcpd_ctx *ctx) {
     return PCPD_OK;
 }
 
+int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
+                     uint64_t t0, uint64_t *dev_lattice, const uint64_t *times, uint32_t n_times,
+                     pcpd_counts *out, void *hip_stream) {
+    int v = validate(cfg, inst, n_inst, /*check_init=*/false);
+    if (v != PCPD_OK) return v;
+    if (!dev_lattice || (!times && n_times) || (!out && n_times)) return PCPD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dev_lattice) % sizeof(uint64_t) != 0) return PCPD_EINVAL;
+    for (uint32_t r = 0; r < n_times; ++r)
+        if (times[r] < t0 || (r > 0 && times[r] <= times[r - 1])) return PCPD_EINVAL;
+    if (overflow_steps(t0, 0, cfg->B)) return PCPD_EOVERFLOW;
+    if (n_times && overflow_steps(times[n_times - 1], 0, cfg->B)) return PCPD_EOVERFLOW;
+    PhaseShape shape{};
+    uint32_t pmax = 0;
+    if (!default_shape(static_cast<uint32_t>(cfg->model), cfg->B, &shape, &pmax))
+        return PCPD_EINVAL;
+    uint64_t total = 0;
+    const std::vector<LatDesc> lats = plan_lats(cfg, inst, n_inst, &total);
+    if (total > kNaWords || lats.size() > kNaRings) return PCPD_ELIMIT;
+    if (static_cast<uint64_t>(n_times) * lats.size() > kNaRecords) return PCPD_ELIMIT;
+    const std::vector<TileDesc> tiles = plan_tiles(lats, shape);
+    const std::vector<DenChunk> chunks = plan_chunks(lats);
+    if (tiles.size() > kNaTiles || chunks.size() > kNaChunks) return PCPD_ELIMIT;
+    if (n_times == 0) return PCPD_OK;
+
+    unsigned char *ws = nullptr;
+    hipError_t e = noalloc_workspace(&ws);
+    if (e != hipSuccess) return fail(nullptr, e);
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+
+    // A context whose two lattice copies are the caller's words and the
+    // workspace's spare copy, and whose tables live in the workspace. It
+    // owns nothing and is never released.
+    pcpd_ctx c;
+    c.n = cfg->model;
+    c.B = cfg->B;
+    c.planes = cfg->planes;
+    c.n_inst = n_inst;
+    c.nlat = static_cast<uint32_t>(lats.size());
+    c.total_words = total;
+    c.stream = stream;
+    c.buf[0] = dev_lattice;
+    c.buf[1] = reinterpret_cast<uint64_t *>(ws);
+    c.cur = 0;
+    c.d_lats = reinterpret_cast<LatDesc *>(ws + kNaOffLats);
+    c.d_tiles = reinterpret_cast<TileDesc *>(ws + kNaOffTiles);
+    c.ntiles = static_cast<uint32_t>(tiles.size());
+    c.d_chunks = reinterpret_cast<DenChunk *>(ws + kNaOffChunks);
+    c.nchunks = static_cast<uint32_t>(chunks.size());
+    c.d_counts = reinterpret_cast<Counts *>(ws + kNaOffCounts);
+    c.count_slots = n_times;
+    c.d_clock = reinterpret_cast<uint64_t *>(ws + kNaOffClock);
+    c.shape = shape;
+    c.phase_max = pmax;
+
+    // The host tables are read by the copies before this call returns (it
+    // synchronises below). Every count record is cleared by a kernel before
+    // it is summed into, and the clock is written here, so nothing left in
+    // the workspace by an earlier call is read.
+    if ((e = hipMemcpyAsync(c.d_lats, lats.data(), lats.size() * sizeof(LatDesc),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c.d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c.d_chunks, chunks.data(), chunks.size() * sizeof(DenChunk),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = pcpd::launch_fill(c.d_clock, 1, t0 * cfg->B, stream)) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        return fail(nullptr, e);
+    }
+    std::vector<BatchOp> ops;
+    uint64_t at = t0;
+    for (uint32_t r = 0; r < n_times; ++r) {
+        ops.push_back(BatchOp{times[r] - at, static_cast<int32_t>(r)});
+        at = times[r];
+    }
+    int cur = 0;
+    e = enqueue_ops(&c, ops, stream, false, &cur);
+    if (e == hipSuccess && cur != 0)  // the last phase wrote the spare copy
+        e = hipMemcpyAsync(dev_lattice, c.buf[1], total * sizeof(uint64_t),
+                           hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, c.d_counts, static_cast<size_t>(n_times) * c.nlat * sizeof(Counts),
+                           hipMemcpyDeviceToHost, stream);
+    const hipError_t es = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = es;
+    return fail(nullptr, e);
+}
+
 const char *pcpd_strerror(int status) {
     switch (status) {
         case PCPD_OK: return "success";
@@ -789,6 +953,7 @@ const char *pcpd_strerror(int status) {
         case PCPD_EDEVICE: return "device error";
         case PCPD_ESTATE: return "context unusable after an earlier device error";
         case PCPD_EOVERFLOW: return "substep counter overflow";
+        case PCPD_ELIMIT: return "exceeds the fixed workspace of the allocation-free run";
         default: return "unknown status";
     }
 }

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libpcpd.so")
 
 OPT_GRAPH = 1
 PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
+PCPD_ELIMIT = -6
+NOALLOC_MAX_WORDS = 1 << 22
 DP, PCPD, TCPD, QCPD = 1, 2, 3, 4
 INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
 
@@ -51,7 +53,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcpd_run",
            "pcpd_get_lattice", "pcpd_set_lattice", "pcpd_time", "pcpd_sync",
            "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_set_options", "pcpd_autotune",
-           "pcpd_profile", "pcpd_profile_read",
+           "pcpd_profile", "pcpd_profile_read", "pcpd_run_noalloc",
            "pcpd_free", "pcpd_strerror"]
 MLP_EXPORTS = ["pcpd_mlp_init", "pcpd_mlp_get_params", "pcpd_mlp_set_params", "pcpd_mlp_predict",
                "pcpd_mlp_grads", "pcpd_mlp_train_step", "pcpd_mlp_free"]
@@ -80,6 +82,8 @@ def load_library(path: str = LIB_PATH):
         "pcpd_autotune": ([vp, u32, P(Tuning)], ctypes.c_int),
         "pcpd_profile": ([vp, ctypes.c_int], ctypes.c_int),
         "pcpd_profile_read": ([vp, P(ctypes.c_double), P(u64)], ctypes.c_int),
+        "pcpd_run_noalloc": ([P(Config), P(InstanceC), u32, u64, vp, P(u64), u32, P(CountsC), vp],
+                             ctypes.c_int),
         "pcpd_free": ([vp], ctypes.c_int),
         "pcpd_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "pcpd_mlp_init": ([P(vp), u32, P(Device)], ctypes.c_int),
@@ -259,6 +263,30 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def run_noalloc(model: int, B: int, planes: int, seed: int, instances, t0: int,
+                lattice: torch.Tensor, times: Sequence[int]) -> np.ndarray:
+    """pcpd_run_noalloc: advance the lattice held in `lattice` (a contiguous
+    int64 CUDA tensor of planes * sum L words, instance-major then
+    plane-major) from step t0 through `times`, in place, without any device
+    allocation; returns uint64 [n_times, n_inst, planes, 3] like Sim.run."""
+    instances = list(instances)
+    words = planes * sum(int(i.L) for i in instances)
+    if not (isinstance(lattice, torch.Tensor) and lattice.is_cuda and lattice.dtype == torch.int64
+            and lattice.is_contiguous() and lattice.numel() == words):
+        raise ValueError(f"lattice must be a contiguous int64 CUDA tensor of {words} words")
+    cfg = Config(int(model), int(B), int(planes), int(seed))
+    arr, keep = _instances(instances, planes)
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
+    out = (CountsC * (len(t) * len(instances) * planes))()
+    with torch.cuda.device(lattice.device):
+        stream = torch.cuda.current_stream(lattice.device).cuda_stream
+        _check(_lib.pcpd_run_noalloc(ctypes.byref(cfg), arr, len(instances), int(t0),
+                                     ctypes.c_void_p(lattice.data_ptr()), _u64p(t), len(t), out,
+                                     ctypes.c_void_p(stream)), "pcpd_run_noalloc")
+    del keep
+    return np.frombuffer(out, dtype=np.uint64).reshape(len(t), len(instances), planes, 3).copy()
 
 
 def _dev_f32(t, shape, name):

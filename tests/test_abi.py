@@ -106,3 +106,29 @@ def test_overflowing_start_time_is_rejected(mod):
     ctx = ctypes.c_void_p()
     rc = mod._lib.pcpd_init(ctypes.byref(ctx), ctypes.byref(cfg), inst, 1, 2**64 // 64 + 1, None)
     assert rc == -5
+
+
+def test_noalloc_run_checks_its_limits_before_any_device_work(mod):
+    """pcpd_run_noalloc validates like pcpd_init + pcpd_run and refuses what
+    exceeds its fixed workspace with PCPD_ELIMIT, all before touching a
+    device (here there is none)."""
+    lib = mod._lib
+    assert lib.pcpd_strerror(-6).startswith(b"exceeds the fixed workspace")
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced on these paths
+    times = (mod.u64 * 2)(5, 9)
+    out = (mod.CountsC * 8)()
+    cfg = _cfg(mod, planes=2)
+    big = _inst(mod, L=mod.NOALLOC_MAX_WORDS)          # 2 planes: twice the limit
+    assert lib.pcpd_run_noalloc(ctypes.byref(cfg), big, 1, 0, fake, times, 2, out, None) == -6
+    one = _cfg(mod, planes=1)
+    ok = _inst(mod, L=1024)
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, None, times, 2, out, None) == -1
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 6, fake, times, 2, out, None) == -1
+    desc = (mod.u64 * 2)(9, 5)
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, fake, desc, 2, out, None) == -1
+    bad = _inst(mod, p=2.0)
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), bad, 1, 0, fake, times, 2, out, None) == -1
+    late = (mod.u64 * 1)(2**64 // 64 + 1)
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, fake, late, 1, out, None) == -5
+    # no records: nothing to do, the lattice is left as it is
+    assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, fake, None, 0, None, None) == 0
