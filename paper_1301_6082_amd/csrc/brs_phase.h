@@ -1,0 +1,603 @@
+// brs_phase.h -- gfx950 phase kernel of the multispin block-synchronous sweep,
+// included by one translation unit per model (phase_n1.hip .. phase_n4.hip).
+//
+//
+// Data layout in HBM: one uint64 word per site, bit b = sample b; each
+// (instance, plane) is a ring of L consecutive words (natural site order);
+// two copies of the whole lattice alternate as source and destination.
+//
+// brs_phase: one workgroup owns one tile of a ring: `kint` interior blocks of
+// B sites plus `hb` halo blocks on each side. It loads the tile into LDS,
+// runs S consecutive substeps there, and writes the interior back. Within a
+// substep every block is attempted at the same local site o (paper Sec. 3),
+// one lane per block. After S substeps a halo of (n+1)*S sites per side has
+// absorbed every influence from outside the tile, because one attempt reads
+// and writes only sites j-1..j+n; halo windows are computed redundantly with
+// the same counter-based draws as their owners, so the interior is exact.
+// Two consecutive substeps whose windows touch disjoint sites commute; such
+// pairs are applied in one interval between workgroup barriers.
+//
+// LDS layout: offset-major, word (block c, local site o) at o*ldw + c. All
+// lanes of a substep touch the same row o, consecutive columns: no bank
+// conflicts. ldw is odd so the row-major HBM<->LDS copies spread over banks,
+// and leaves three spare columns past the tile.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pcpd_internal.h"
+#include "philox.h"
+
+namespace pcpd {
+namespace {
+
+// Local site of substep s: o = floor(x0 * B / 2^32) of draw 7, window 0.
+__device__ __forceinline__ uint32_t substep_site(const LatDesc &ld, uint64_t s, uint32_t B) {
+    const U4 x = philox10(U4{0u, (ld.plane << 3) | 7u, static_cast<uint32_t>(s),
+                             static_cast<uint32_t>(s >> 32)},
+                          ld.key0, ld.key1);
+    return static_cast<uint32_t>((static_cast<uint64_t>(x.x) * B) >> 32);
+}
+
+// Truth table of a three-input bitwise function for v_bitop3_b32: bit
+// (4*a + 2*b + c) of the table is f(a, b, c). Evaluated on the canonical
+// operand patterns a = 0xF0, b = 0xCC, c = 0xAA.
+template <typename F>
+constexpr uint32_t lut3(F f) {
+    return f(0xF0u, 0xCCu, 0xAAu) & 0xFFu;
+}
+
+// Probability-q decision, one 32-bit half: sample bit fires iff
+// (2*a + b) * 2^32 + g < KH * 2^32 + kl, a = bit of X1, b = bit of X2,
+// t = all-ones iff the shared tail g < kl. For each integer part KH of the
+// threshold the decision is a fixed function of (a, b, t):
+//   KH=0: u == 0 and t;  KH=1: u == 0, or u == 1 and t;  KH=2: u <= 1, or u == 2 and t;
+//   KH=3: u <= 2, or t;  KH=4: always (q = 1).
+template <int KH>
+struct Decide {
+    static constexpr uint32_t lut() {
+        if constexpr (KH == 0) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a & ~b & t; });
+        else if constexpr (KH == 1) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a & (~b | t); });
+        else if constexpr (KH == 2) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a | (~b & t); });
+        else if constexpr (KH == 3) return lut3([](uint32_t a, uint32_t b, uint32_t t) { return ~a | ~b | t; });
+        else return 0xFFu;
+    }
+    __device__ static __forceinline__ uint32_t half(uint32_t a, uint32_t b, uint32_t t) {
+        if constexpr (KH >= 4) return 0xFFFFFFFFu;
+        else return __builtin_amdgcn_bitop3_b32(a, b, t, lut());
+    }
+};
+
+struct W2 {
+    uint32_t lo, hi;
+};
+
+// Decision masks of one window: D (diffusion), Am (annihilation, before the
+// tuple condition) and R (fission direction, 1 = high), as 32-bit halves.
+struct Masks {
+    W2 D, Am, R;
+};
+
+// The ten rounds of the three draws of one window, advanced round by round
+// together: six independent 32x32->64 products per round. The first round's
+// products are identical for the three draws (they differ only in counter
+// word 1) and are computed once by the compiler.
+__device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
+            const uint64_t pb = static_cast<uint64_t>(c[j].z) * kMulB;
+            U4 nx;
+            if (r < 2) {
+                // the first two rounds have operands that are uniform across the
+                // wavefront (counter words 1-3 and the key); plain XORs let the
+                // compiler keep those on the scalar unit, which the vector-only
+                // three-input XOR cannot
+                nx.x = static_cast<uint32_t>(pb >> 32) ^ c[j].y ^ ka;
+                nx.z = static_cast<uint32_t>(pa >> 32) ^ c[j].w ^ kb;
+            } else {
+                nx.x = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c[j].y, ka, 0x96);
+                nx.z = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c[j].w, kb, 0x96);
+            }
+            nx.y = static_cast<uint32_t>(pb);
+            nx.w = static_cast<uint32_t>(pa);
+            c[j] = nx;
+        }
+        ka += kWeylA;
+        kb += kWeylB;
+    }
+}
+
+template <int KDH, int KPH>
+__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
+    const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
+    const uint32_t q8 = ld.plane << 3;
+    U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
+    philox10_x3(x, ld.key0, ld.key1);
+    const U4 &d = x[0], &a = x[1], &r = x[2];
+    const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
+    const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
+    Masks m;
+    // X1 = x | y << 32, X2 = z | w << 32
+    m.D.lo = Decide<KDH>::half(d.x, d.z, td);
+    m.D.hi = Decide<KDH>::half(d.y, d.w, td);
+    m.Am.lo = Decide<KPH>::half(a.x, a.z, ta);
+    m.Am.hi = Decide<KPH>::half(a.y, a.w, ta);
+    m.R.lo = r.x;
+    m.R.hi = r.y;
+    return m;
+}
+
+// Pin the masks in registers at this point of the program. Before a barrier,
+// the arithmetic that produces them cannot sink into the next interval, where
+// it would no longer overlap the LDS latency of this interval's update.
+__device__ __forceinline__ void pin(Masks &m) {
+    asm volatile("" : "+v"(m.D.lo), "+v"(m.D.hi), "+v"(m.Am.lo), "+v"(m.Am.hi), "+v"(m.R.lo),
+                      "+v"(m.R.hi));
+}
+
+// Bit-sliced attempt on one 32-bit half of a window; w[0] = site j-1,
+// w[1..N] = the tuple j..j+N-1, w[N+1] = site j+N.
+template <int N>
+__device__ __forceinline__ void attempt(uint32_t (&w)[N + 2], uint32_t D, uint32_t Am, uint32_t R) {
+    uint32_t P = w[1];
+#pragma unroll
+    for (int i = 2; i <= N; ++i) P &= w[i];
+    const uint32_t a = w[1], b = w[2];
+    w[1] = (D & b) | (~D & a);  // diffusion: swap j, j+1 where D
+    w[2] = (D & a) | (~D & b);
+    const uint32_t nP = ~D & P;       // tuple present, no diffusion
+    const uint32_t A = nP & Am;       // annihilation
+    const uint32_t F = nP & ~Am;      // fission
+#pragma unroll
+    for (int i = 1; i <= N; ++i) w[i] &= ~A;
+    w[N + 1] |= F & R;   // high: site j+N
+    w[0] |= F & ~R;      // low: site j-1
+}
+
+// LDS word offsets (in words) of the window of substep site o, relative to
+// the lane's column: site o-1+m sits in row (o-1+m) mod B of column c-1, c or
+// c+1. Integer arithmetic only, so that it stays on the scalar unit.
+template <int N>
+__device__ __forceinline__ void window_offsets(uint32_t o, uint32_t B, uint32_t ldw,
+                                               int (&base)[N + 2]) {
+    const int W = static_cast<int>(B * ldw) - 1;  // one row-block back plus one column
+#pragma unroll
+    for (int m = 0; m < N + 2; ++m) {
+        const int r = static_cast<int>(o) - 1 + m;
+        const int below = static_cast<int>(static_cast<uint32_t>(r) >> 31);            // r < 0
+        const int above = 1 - static_cast<int>(static_cast<uint32_t>(r - static_cast<int>(B)) >> 31);  // r >= B
+        base[m] = r * static_cast<int>(ldw) + (below - above) * W;
+    }
+}
+
+// Apply the attempt of substep site o to the lane's window in LDS (see
+// run_substeps for the two addressing cases). mid() runs after the window's
+// loads are issued and before their values are used: arithmetic placed there
+// fills the LDS latency.
+template <int N, typename Mid>
+__device__ __forceinline__ void apply_window(uint64_t *lds, const Masks &m, uint32_t o,
+                                             uint32_t c, uint32_t col_in, bool ok_lo,
+                                             bool ok_hi, uint32_t trash, uint32_t B,
+                                             uint32_t ldw, Mid &&mid) {
+    uint32_t wl[N + 2], wh[N + 2];
+    if (o - 1u < B - 1u - N) {
+        // window rows o-1 .. o+N inside the lane's own column: one address
+        // plus multiples of the pitch (all but (N+1)/B of the substeps)
+        uint64_t *w = lds + ((o - 1u) * ldw + col_in);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k) {
+            const uint64_t v = w[k * ldw];
+            wl[k] = static_cast<uint32_t>(v);
+            wh[k] = static_cast<uint32_t>(v >> 32);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of mid()
+        mid();
+        attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
+        attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k)
+            w[k * ldw] = static_cast<uint64_t>(wl[k]) | (static_cast<uint64_t>(wh[k]) << 32);
+    } else {
+        // window sites o-1 .. o+N of block c spill into block c-1 when o == 0
+        // and into block c+1 when o+N >= B
+        const bool ok = !(o == 0u && !ok_lo) && !(o + N >= B && !ok_hi);
+        const int col = static_cast<int>(ok ? c : trash);
+        int base[N + 2];
+        window_offsets<N>(o, B, ldw, base);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k) {
+            const uint64_t v = lds[base[k] + col];
+            wl[k] = static_cast<uint32_t>(v);
+            wh[k] = static_cast<uint32_t>(v >> 32);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of mid()
+        mid();
+        attempt<N>(wl, m.D.lo, m.Am.lo, m.R.lo);
+        attempt<N>(wh, m.D.hi, m.Am.hi, m.R.hi);
+#pragma unroll
+        for (int k = 0; k < N + 2; ++k)
+            lds[base[k] + col] = static_cast<uint64_t>(wl[k]) | (static_cast<uint64_t>(wh[k]) << 32);
+    }
+}
+
+// True when the windows of two substeps with local sites oa and ob touch
+// disjoint sites: the cyclic distance of oa and ob within a block is at least
+// N+2, the window length. Every block uses the same local site, so the two
+// substeps then commute and may be applied in either order or together.
+template <int N>
+__device__ __forceinline__ bool windows_disjoint(uint32_t oa, uint32_t ob, uint32_t B) {
+    uint32_t d = ob - oa;
+    if (static_cast<int32_t>(d) < 0) d += B;  // (ob - oa) mod B, with oa, ob < B
+    const uint32_t e = B - d;                 // (oa - ob) mod B, or B when d == 0
+    return d >= N + 2u && e >= N + 2u;
+}
+
+// S substeps of one tile held in LDS (see the file comment), by two teams
+// of lanes, each with one lane per block; team t applies the substeps
+// it = t, t+2, t+4, ... Substeps are taken in pairs (it, it+1), it even:
+// when their windows are disjoint (windows_disjoint; at B = 64 and N = 2
+// all but 7 of 64 pairs) both teams apply their substep in the same interval
+// between two barriers; otherwise team 0 applies its substep in one interval
+// and team 1 in the next. Each team then draws the masks of its next
+// substep between the loads and the arithmetic of its update, which fills
+// the LDS latency. The two teams run their own loops (no register copies
+// between the branches) and pass the same number of barriers. Draws past
+// the phase end are computed and dropped.
+// Each wavefront draws the local sites of 64 substeps at a time, one per
+// lane, and reads them back with v_readlane.
+// Window rows o-1 .. o+N lie inside the lane's own column when
+// 1 <= o <= B-1-N; otherwise (a uniform branch, (N+1)/B of the substeps) the
+// window spills into a neighbouring column and each word has its own
+// address. Lanes whose window would leave the loaded columns (block 0 when
+// o == 0, the last block when o+N >= B, lanes past the tile) work on the
+// spare columns trash-1 .. trash+1 instead, so no branch depends on the lane.
+template <int N, int KDH, int KPH>
+__device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+                                             uint32_t c, uint32_t team, uint32_t ncols,
+                                             uint32_t trash, uint64_t s0, uint32_t S, uint32_t B,
+                                             uint32_t ldw) {
+    const uint32_t lane = __lane_id();
+    const bool active = c < ncols;
+    const bool ok_lo = active && c != 0u;          // a spill into block c-1 stays in the tile
+    const bool ok_hi = active && c + 1u != ncols;  // a spill into block c+1 stays in the tile
+    const uint32_t col_in = active ? c : trash;    // column of a window inside one column
+    // The masks alternate between two register sets (m0, m1) over a pair of
+    // pairs, so that no register copies are needed inside the loop.
+    Masks m0 = window_masks<KDH, KPH>(ld, kg, s0 + team), m1{};
+    if (team == 0u) {
+        // one pair: apply substep it0+j, draw substep it0+j+2
+        auto step = [&](uint32_t sites, uint32_t it0, uint32_t n, uint32_t j, const Masks &use,
+                        Masks &make) {
+            const uint32_t oa = __builtin_amdgcn_readlane(sites, j);
+            const bool split = j + 1u < n &&
+                               !windows_disjoint<N>(oa, __builtin_amdgcn_readlane(sites, j + 1u), B);
+            auto draw = [&] {
+                make = window_masks<KDH, KPH>(ld, kg, s0 + it0 + j + 2u);
+                pin(make);
+            };
+            apply_window<N>(lds, use, oa, c, col_in, ok_lo, ok_hi, trash, B, ldw, draw);
+            __syncthreads();
+            if (split) __syncthreads();  // team 1 applies its substep alone
+        };
+        for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+            const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
+            const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+            uint32_t j = 0;
+            for (; j + 2u < n; j += 4u) {
+                step(sites, it0, n, j, m0, m1);
+                step(sites, it0, n, j + 2u, m1, m0);
+            }
+            if (j < n) {
+                step(sites, it0, n, j, m0, m1);
+                m0 = m1;
+            }
+        }
+    } else {
+        // one pair: apply substep it0+j+1 (if any), draw substep it0+j+3
+        auto step = [&](uint32_t sites, uint32_t it0, uint32_t n, uint32_t j, const Masks &use,
+                        Masks &make) {
+            const bool has_b = j + 1u < n;
+            const uint32_t ob = __builtin_amdgcn_readlane(sites, has_b ? j + 1u : j);
+            const bool split =
+                has_b && !windows_disjoint<N>(__builtin_amdgcn_readlane(sites, j), ob, B);
+            if (split) __syncthreads();  // after team 0's substep
+            auto draw = [&] {
+                make = window_masks<KDH, KPH>(ld, kg, s0 + it0 + j + 3u);
+                pin(make);
+            };
+            if (has_b)
+                apply_window<N>(lds, use, ob, c, col_in, ok_lo, ok_hi, trash, B, ldw, draw);
+            else
+                draw();
+            __syncthreads();
+        };
+        for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+            const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);
+            const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+            uint32_t j = 0;
+            for (; j + 2u < n; j += 4u) {
+                step(sites, it0, n, j, m0, m1);
+                step(sites, it0, n, j + 2u, m1, m0);
+            }
+            if (j < n) {
+                step(sites, it0, n, j, m0, m1);
+                m0 = m1;
+            }
+        }
+    }
+}
+
+template <int N, int KDH>
+__device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
+                                            uint32_t kg, uint32_t c, uint32_t team, uint32_t ncols,
+                                            uint32_t trash,
+                                            uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
+    switch (ld.kp_hi) {
+        case 0: run_substeps<N, KDH, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 1: run_substeps<N, KDH, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 2: run_substeps<N, KDH, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 3: run_substeps<N, KDH, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        default: run_substeps<N, KDH, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+    }
+}
+
+// Words moved per lane per batch between HBM and LDS: independent loads in
+// flight hide the memory latency.
+constexpr int kCopyBatch = 16;
+
+// Two consecutive sites of one block, moved as one 16-byte access.
+struct alignas(16) WordPair {
+    uint64_t a, b;
+};
+
+// Copy `total` words of a tile, ring blocks kfirst, kfirst+1, ... (mod nb),
+// from HBM (natural order) into LDS column-per-block. Lane i handles words
+// i, i+nthr, ...; (column, row, ring block) advance incrementally.
+__device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restrict__ ring,
+                                          uint32_t kfirst, uint32_t nb, uint32_t total, uint32_t B,
+                                          uint32_t ldw, uint32_t tid, uint32_t nthr) {
+    const uint32_t cstep = nthr / B, ostep = nthr - cstep * B, kstep = cstep % nb;
+    uint32_t c = tid / B, o = tid - c * B;
+    uint32_t kg = (kfirst + c) % nb;
+    for (uint32_t i0 = tid; i0 < total; i0 += kCopyBatch * nthr) {
+        uint64_t v[kCopyBatch];
+        uint32_t a[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            a[u] = o * ldw + c;
+            v[u] = (i0 + u * nthr < total) ? ring[static_cast<uint64_t>(kg) * B + o] : 0ull;
+            c += cstep;
+            o += ostep;
+            kg += kstep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+                ++kg;
+            }
+            if (kg >= nb) kg -= nb;
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * nthr < total) lds[a[u]] = v[u];
+    }
+}
+
+// load_tile for an even B and a 16-byte aligned ring: lane i handles the
+// site pairs (2i, 2i+1), (2i+2*nthr, ...), ..., so a tile of up to
+// 2*kCopyBatch*nthr words arrives in one round trip. FIXED_ROW: 2*nthr is a
+// multiple of B, so every pair of a lane lies in the same row (the default
+// shapes); the row-wrap test then drops out of the loop.
+template <bool FIXED_ROW>
+__device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *__restrict__ ring,
+                                                uint32_t kfirst, uint32_t nb, uint32_t total,
+                                                uint32_t B, uint32_t ldw, uint32_t tid,
+                                                uint32_t nthr) {
+    const WordPair *rp = reinterpret_cast<const WordPair *>(ring);
+    const uint32_t step = 2u * nthr;
+    const uint32_t cstep = step / B, ostep = step - cstep * B, kstep = cstep % nb;
+    uint32_t c = (2u * tid) / B, o = 2u * tid - c * B;
+    uint32_t kg = (kfirst + c) % nb;
+    const uint32_t half = B >> 1;
+    for (uint32_t i0 = 2u * tid; i0 < total; i0 += kCopyBatch * step) {
+        WordPair v[kCopyBatch];
+        uint32_t a[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            a[u] = o * ldw + c;
+            if (i0 + u * step < total) v[u] = rp[static_cast<uint64_t>(kg) * half + (o >> 1)];
+            c += cstep;
+            kg += kstep;
+            if constexpr (!FIXED_ROW) {
+                o += ostep;
+                if (o >= B) {
+                    o -= B;
+                    ++c;
+                    ++kg;
+                }
+            }
+            if (kg >= nb) kg -= nb;
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * step < total) {
+                lds[a[u]] = v[u].a;
+                lds[a[u] + ldw] = v[u].b;
+            }
+    }
+}
+
+// Copy the interior columns hb .. hb+total/B-1 of the tile back to HBM, where
+// they are `total` consecutive words starting at `out`.
+__device__ __forceinline__ void store_interior(uint64_t *__restrict__ out, const uint64_t *lds,
+                                               uint32_t hb, uint32_t total, uint32_t B, uint32_t ldw,
+                                               uint32_t tid, uint32_t nthr) {
+    const uint32_t cstep = nthr / B, ostep = nthr - cstep * B;
+    uint32_t c = tid / B, o = tid - c * B;
+    for (uint32_t i0 = tid; i0 < total; i0 += kCopyBatch * nthr) {
+        uint64_t v[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            v[u] = (i0 + u * nthr < total) ? lds[o * ldw + hb + c] : 0ull;
+            c += cstep;
+            o += ostep;
+            if (o >= B) {
+                o -= B;
+                ++c;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * nthr < total) out[i0 + u * nthr] = v[u];
+    }
+}
+
+// store_interior for an even B and a 16-byte aligned destination, one site
+// pair per lane and access; FIXED_ROW as for load_tile_pairs.
+template <bool FIXED_ROW>
+__device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
+                                                     const uint64_t *lds, uint32_t hb,
+                                                     uint32_t total, uint32_t B, uint32_t ldw,
+                                                     uint32_t tid, uint32_t nthr) {
+    WordPair *op = reinterpret_cast<WordPair *>(out);
+    const uint32_t step = 2u * nthr;
+    const uint32_t cstep = step / B, ostep = step - cstep * B;
+    uint32_t c = (2u * tid) / B, o = 2u * tid - c * B;
+    for (uint32_t i0 = 2u * tid; i0 < total; i0 += kCopyBatch * step) {
+        WordPair v[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u) {
+            if (i0 + u * step < total) {
+                v[u].a = lds[o * ldw + hb + c];
+                v[u].b = lds[(o + 1u) * ldw + hb + c];
+            }
+            c += cstep;
+            if constexpr (!FIXED_ROW) {
+                o += ostep;
+                if (o >= B) {
+                    o -= B;
+                    ++c;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; ++u)
+            if (i0 + u * step < total) op[(i0 + u * step) >> 1] = v[u];
+    }
+}
+
+// LDS row pitch of the default tile (128 columns plus three spare, odd).
+constexpr uint32_t kDefaultPitch = 131;
+
+// One workgroup per tile, two lanes per block (the two teams). At most two
+// wavefronts per SIMD: with 128-block tiles two workgroups share a CU, with
+// 256-block tiles one does. PITCH is the LDS row pitch as a compile-time
+// constant (0: the ldw_arg argument); with a constant pitch the rows of a
+// window are immediate offsets from one address.
+template <int N, uint32_t PITCH>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+          const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
+          const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
+          uint32_t cols, uint32_t ldw_arg) {
+    const uint32_t ldw = PITCH ? PITCH : ldw_arg;
+    // first substep of the phase: the context's device clock plus this
+    // launch's offset, so that a captured sequence of launches is valid at
+    // any starting time
+    const uint64_t s0 = *clock + s_off;
+    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
+    const TileDesc td = tiles[blockIdx.x];
+    const LatDesc ld = lats[td.lat];
+    const uint32_t nb = ld.nblocks;
+    const uint32_t ncols = td.kint + 2u * hb;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nthr = blockDim.x;
+    // first loaded block: (k0 - hb) mod nb, without going negative
+    const uint32_t kfirst = static_cast<uint32_t>(
+        (static_cast<uint64_t>(td.k0) + static_cast<uint64_t>(nb) * ((hb + nb - 1u) / nb) - hb) %
+        nb);
+
+    // even B and 16-byte aligned buffers: tile copies move site pairs
+    const bool pairs = (B & 1u) == 0u &&
+                       ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0u;
+
+    // ---- load tile + halo: consecutive lanes read consecutive words
+    const bool fixed_row = (2u * nthr) % B == 0u;
+    if (pairs && fixed_row)
+        load_tile_pairs<true>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    else if (pairs)
+        load_tile_pairs<false>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    else
+        load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
+    __syncthreads();
+
+    // ---- S substeps in LDS, one window (block) per lane
+    {
+        // half is a multiple of the wavefront size, so the team is uniform
+        // per wavefront and its branches stay on the scalar unit
+        const uint32_t half = nthr >> 1;
+        const uint32_t team = __builtin_amdgcn_readfirstlane(tid >= half ? 1u : 0u);
+        const uint32_t c = tid - team * half;
+        const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
+        uint32_t kg = kfirst + c;
+        if (kg >= nb) kg %= nb;
+        switch (ld.kd_hi) {
+            case 0: dispatch_kp<N, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 1: dispatch_kp<N, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 2: dispatch_kp<N, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 3: dispatch_kp<N, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            default: dispatch_kp<N, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        }
+    }
+
+    // ---- write the interior back; it is contiguous in the ring
+    uint64_t *out = dst + ld.base + static_cast<uint64_t>(td.k0) * B;
+    if (pairs && fixed_row)
+        store_interior_pairs<true>(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+    else if (pairs)
+        store_interior_pairs<false>(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+    else
+        store_interior(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
+}
+
+template <int N, uint32_t PITCH>
+hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                         const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                         uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                         hipStream_t stream) {
+    const size_t lds = phase_lds_bytes(B, sh.ldw, S);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(kMaxLdsBytes));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((brs_phase<N, PITCH>), dim3(ntiles), dim3(sh.threads), lds, stream, src,
+                       dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
+    return hipGetLastError();
+}
+
+// The default PCPD tile runs a copy of the kernel compiled for its pitch;
+// every other model and shape takes the pitch as an argument.
+template <int N>
+hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                          hipStream_t stream) {
+    if constexpr (N == 2) {
+        if (sh.ldw == kDefaultPitch)
+            return launch_kernel<N, kDefaultPitch>(src, dst, lats, tiles, ntiles, clock, s_off, S,
+                                                   B, sh, stream);
+    }
+    return launch_kernel<N, 0>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+}
+
+}  // namespace
+}  // namespace pcpd

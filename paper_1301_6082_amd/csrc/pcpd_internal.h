@@ -63,6 +63,18 @@ hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc
                         uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &shape,
                         hipStream_t stream);
 
+// The phase launch of one model (n = 1..4), each in its own translation unit.
+#define PCPD_PHASE_LAUNCHER(name)                                                             \
+    hipError_t name(const uint64_t *src, uint64_t *dst, const LatDesc *lats,                  \
+                    const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,            \
+                    uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &shape,          \
+                    hipStream_t stream)
+PCPD_PHASE_LAUNCHER(launch_phase_model1);
+PCPD_PHASE_LAUNCHER(launch_phase_model2);
+PCPD_PHASE_LAUNCHER(launch_phase_model3);
+PCPD_PHASE_LAUNCHER(launch_phase_model4);
+#undef PCPD_PHASE_LAUNCHER
+
 // *clock += delta, on the device.
 hipError_t launch_advance_clock(uint64_t *clock, uint64_t delta, hipStream_t stream);
 
