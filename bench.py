@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 OPS_PER_WORD_UPDATE = {1: 129, 2: 131, 3: 135, 4: 139}
 PEAK_SLOTS = 256 * 64 * 2.4e9          # CUs x 64 lanes x 2.4 GHz = 3.93e13 ops/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "brs_phase_pcpd_L2p20_traffic.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "sweep.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1301_6082_amd", "csrc", "brs_phase.h")
 
 
 def parse():
@@ -59,12 +59,15 @@ def parse():
     ap.add_argument("--workload", choices=("cfg2", "cfg3", "cfg4"), default="cfg2")
     ap.add_argument("--autotune", action="store_true",
                     help="time the library's tile shapes on the workload first (untimed)")
+    ap.add_argument("--teams", type=int, default=0, choices=(0, 2, 4),
+                    help="lanes per block of the phase kernel (0 = the library's default)")
     return ap.parse_args()
 
 
 def kernel_traffic(tile):
     """HBM bytes per phase launch from the committed counter profile, if it
-    was taken on the current kernel source and tile shape; else None."""
+    was taken on the current kernel source and tile shape (columns x substeps
+    x teams); else None."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -75,7 +78,7 @@ def kernel_traffic(tile):
     digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if fields.get("kernel_sha256", "").strip() != digest:
         return None
-    if fields.get("tile", "").strip() != f"{tile[0]}x{tile[1]}":
+    if fields.get("tile", "").strip() != f"{tile[0]}x{tile[1]}x{tile[2]}":
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -139,6 +142,8 @@ def main():
         del src, dst
 
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
+    if args.teams:
+        sim.set_tuning(0, 0, args.teams)
     if args.autotune:
         sim.autotune()
 
@@ -196,7 +201,8 @@ def main():
                         round(max(i.p for i in wl.instances), 4)], "B": wl.B}
     config.update({"mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
                    "records": "the workload's log-spaced record times, plus each step end",
-                   "tile_cols": tuning[0], "phase_max": tuning[1], "autotuned": args.autotune})
+                   "tile_cols": tuning[0], "phase_max": tuning[1], "teams": tuning[2],
+                   "autotuned": args.autotune})
 
     out = {
         "metric": "site-updates/sec (samples x sites x MC steps) at 1 GPU",

@@ -108,10 +108,12 @@ typedef struct {
     uint64_t alive;   /* bit b set iff sample b holds at least one particle */
 } pcpd_counts;
 
-/* Kernel shape of the sweep. Results never depend on it. */
+/* Kernel shape of the sweep. Results never depend on it. All three 0 = the
+ * default shape; otherwise a 0 field keeps the context's current value. */
 typedef struct {
-    uint32_t tile_cols;  /* blocks per workgroup tile including the halo; 0 = default */
-    uint32_t phase_max;  /* substeps run while a tile stays in LDS; 0 = default */
+    uint32_t tile_cols;  /* blocks per workgroup tile including the halo */
+    uint32_t phase_max;  /* substeps run while a tile stays in LDS */
+    uint32_t teams;      /* lanes per block, 2 or 4: team t applies substeps t, t+teams, ... */
 } pcpd_tuning;
 
 typedef struct pcpd_ctx pcpd_ctx;

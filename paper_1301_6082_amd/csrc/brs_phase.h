@@ -333,17 +333,115 @@ __device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, u
     }
 }
 
-template <int N, int KDH>
+// Greedy cut of the groups of T consecutive substeps of a batch of 64 into
+// runs of substeps whose windows are pairwise disjoint. Lane i holds the local
+// site of substep i of the batch; it returns the run index of substep i within
+// its group (lanes i & ~(T-1) .. i | (T-1)). The greedy cut of a prefix of a
+// group is the prefix of the group's cut, so a group cut short by the end of
+// a phase takes the run indices of its members as they are.
+template <int N, int T>
+__device__ __forceinline__ uint32_t group_run_index(uint32_t sites, uint32_t B) {
+    const uint32_t lane = __lane_id();
+    const uint32_t base = lane & ~static_cast<uint32_t>(T - 1);
+    const uint32_t pos = lane - base;
+    uint32_t o[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) o[j] = __shfl(sites, static_cast<int>(base) + j, 64);
+    uint32_t seg = 0, start = 0, mine = 0;
+#pragma unroll
+    for (int j = 1; j < T; ++j) {
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < j; ++i)
+            if (static_cast<uint32_t>(i) >= start) ok = ok && windows_disjoint<N>(o[i], o[j], B);
+        if (!ok) {
+            ++seg;
+            start = j;
+        }
+        if (static_cast<uint32_t>(j) == pos) mine = seg;
+    }
+    return mine;
+}
+
+// run_substeps for T teams (T divides 64): team t applies the substeps
+// t, t+T, t+2T, ... Substeps are taken in groups of T consecutive ones; a
+// group is cut into runs of pairwise commuting substeps (group_run_index), and
+// each run is applied in one interval between workgroup barriers, every team
+// of the run at once. A team draws the masks of its next substep (T later)
+// between the loads and the arithmetic of its update. Every wavefront passes
+// the same barriers: each computes the same cut from the same local sites.
+template <int N, int KDH, int KPH, int T>
+__device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+                                                   uint32_t c, uint32_t team, uint32_t ncols,
+                                                   uint32_t trash, uint64_t s0, uint32_t S,
+                                                   uint32_t B, uint32_t ldw) {
+    static_assert(64 % T == 0, "a group must not straddle a batch of 64 local sites");
+    const uint32_t lane = __lane_id();
+    const bool active = c < ncols;
+    const bool ok_lo = active && c != 0u;
+    const bool ok_hi = active && c + 1u != ncols;
+    const uint32_t col_in = active ? c : trash;
+    Masks m0 = window_masks<KDH, KPH>(ld, kg, s0 + team), m1{};
+    auto group = [&](uint32_t sites, uint32_t runs, uint32_t it0, uint32_t n, uint32_t g,
+                     const Masks &use, Masks &make) {
+        const uint32_t k = (n - g < static_cast<uint32_t>(T)) ? n - g : static_cast<uint32_t>(T);
+        const uint32_t nseg = __builtin_amdgcn_readlane(runs, g + k - 1u) + 1u;
+        const bool mine = team < k;
+        const uint32_t myseg = __builtin_amdgcn_readlane(runs, g + (mine ? team : 0u));
+        if (mine) {
+            // the runs before this team's run, its own run, the runs after it
+            for (uint32_t e = 0; e < myseg; ++e) __syncthreads();
+            const uint32_t o = __builtin_amdgcn_readlane(sites, g + team);
+            auto draw = [&] {
+                make = window_masks<KDH, KPH>(ld, kg, s0 + it0 + g + team + T);
+                pin(make);
+            };
+            apply_window<N>(lds, use, o, c, col_in, ok_lo, ok_hi, trash, B, ldw, draw);
+            for (uint32_t e = myseg; e < nseg; ++e) __syncthreads();
+        } else {
+            // no substep of this team in a group cut short by the phase end
+            for (uint32_t e = 0; e < nseg; ++e) __syncthreads();
+        }
+    };
+    for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
+        const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
+        const uint32_t runs = group_run_index<N, T>(sites, B);
+        const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
+        uint32_t g = 0;
+        for (; g + T < n; g += 2u * T) {
+            group(sites, runs, it0, n, g, m0, m1);
+            group(sites, runs, it0, n, g + T, m1, m0);
+        }
+        if (g < n) {
+            group(sites, runs, it0, n, g, m0, m1);
+            m0 = m1;
+        }
+    }
+}
+
+// T = 2 runs the two-team loop above; T = 4 the general one.
+template <int N, int KDH, int KPH, int T>
+__device__ __forceinline__ void run_team_loop(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+                                              uint32_t c, uint32_t team, uint32_t ncols,
+                                              uint32_t trash, uint64_t s0, uint32_t S, uint32_t B,
+                                              uint32_t ldw) {
+    if constexpr (T == 2)
+        run_substeps<N, KDH, KPH>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw);
+    else
+        run_substeps_teams<N, KDH, KPH, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw);
+}
+
+template <int N, int KDH, int T>
 __device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
                                             uint32_t kg, uint32_t c, uint32_t team, uint32_t ncols,
                                             uint32_t trash,
                                             uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
     switch (ld.kp_hi) {
-        case 0: run_substeps<N, KDH, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-        case 1: run_substeps<N, KDH, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-        case 2: run_substeps<N, KDH, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-        case 3: run_substeps<N, KDH, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-        default: run_substeps<N, KDH, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 0: run_team_loop<N, KDH, 0, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 1: run_team_loop<N, KDH, 1, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 2: run_team_loop<N, KDH, 2, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 3: run_team_loop<N, KDH, 3, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        default: run_team_loop<N, KDH, 4, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
     }
 }
 
@@ -494,13 +592,13 @@ __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
 // LDS row pitch of the default tile (128 columns plus three spare, odd).
 constexpr uint32_t kDefaultPitch = 131;
 
-// One workgroup per tile, two lanes per block (the two teams). At most two
-// wavefronts per SIMD: with 128-block tiles two workgroups share a CU, with
-// 256-block tiles one does. PITCH is the LDS row pitch as a compile-time
-// constant (0: the ldw_arg argument); with a constant pitch the rows of a
-// window are immediate offsets from one address.
-template <int N, uint32_t PITCH>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// One workgroup per tile, T lanes per block (the T teams). With 128-block
+// tiles two workgroups share a CU, with 256-block tiles one does: T
+// wavefronts per SIMD. PITCH is the LDS row pitch as a compile-time constant
+// (0: the ldw_arg argument); with a constant pitch the rows of a window are
+// immediate offsets from one address.
+template <int N, uint32_t PITCH, int T>
+__global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
           const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
@@ -538,20 +636,20 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
 
     // ---- S substeps in LDS, one window (block) per lane
     {
-        // half is a multiple of the wavefront size, so the team is uniform
+        // per is a multiple of the wavefront size, so the team is uniform
         // per wavefront and its branches stay on the scalar unit
-        const uint32_t half = nthr >> 1;
-        const uint32_t team = __builtin_amdgcn_readfirstlane(tid >= half ? 1u : 0u);
-        const uint32_t c = tid - team * half;
+        const uint32_t per = nthr / T;
+        const uint32_t team = __builtin_amdgcn_readfirstlane(tid / per);
+        const uint32_t c = tid - team * per;
         const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
         uint32_t kg = kfirst + c;
         if (kg >= nb) kg %= nb;
         switch (ld.kd_hi) {
-            case 0: dispatch_kp<N, 0>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 1: dispatch_kp<N, 1>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 2: dispatch_kp<N, 2>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 3: dispatch_kp<N, 3>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            default: dispatch_kp<N, 4>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 0: dispatch_kp<N, 0, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 1: dispatch_kp<N, 1, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 2: dispatch_kp<N, 2, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            case 3: dispatch_kp<N, 3, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+            default: dispatch_kp<N, 4, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
         }
     }
 
@@ -565,7 +663,7 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         store_interior(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
 }
 
-template <int N, uint32_t PITCH>
+template <int N, uint32_t PITCH, int T>
 hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
@@ -573,30 +671,43 @@ hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats
     const size_t lds = phase_lds_bytes(B, sh.ldw, S);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH, T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(kMaxLdsBytes));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((brs_phase<N, PITCH>), dim3(ntiles), dim3(sh.threads), lds, stream, src,
-                       dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
+    hipLaunchKernelGGL((brs_phase<N, PITCH, T>), dim3(ntiles), dim3(sh.threads), lds, stream,
+                       src, dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
     return hipGetLastError();
 }
 
+template <int N, int T>
+hipError_t launch_teams(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
+                        const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
+                        uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
+                        hipStream_t stream) {
+    if constexpr (N == 2) {
+        if (sh.ldw == kDefaultPitch)
+            return launch_kernel<N, kDefaultPitch, T>(src, dst, lats, tiles, ntiles, clock, s_off,
+                                                      S, B, sh, stream);
+    }
+    return launch_kernel<N, 0, T>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+}
+
 // The default PCPD tile runs a copy of the kernel compiled for its pitch;
-// every other model and shape takes the pitch as an argument.
+// every other model and shape takes the pitch as an argument. Two or four
+// teams per tile.
 template <int N>
 hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                           const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
                           uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
                           hipStream_t stream) {
-    if constexpr (N == 2) {
-        if (sh.ldw == kDefaultPitch)
-            return launch_kernel<N, kDefaultPitch>(src, dst, lats, tiles, ntiles, clock, s_off, S,
-                                                   B, sh, stream);
+    switch (sh.teams) {
+        case 2: return launch_teams<N, 2>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+        case 4: return launch_teams<N, 4>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+        default: return hipErrorInvalidValue;
     }
-    return launch_kernel<N, 0>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
 }
 
 }  // namespace

@@ -121,20 +121,28 @@ int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
 
 // Shape for `cols` LDS columns; hb halo blocks are needed for phase_max
 // substeps: an attempt reaches n+1 sites, so S substeps need (n+1)*S sites.
-bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, PhaseShape *out) {
+bool make_shape(uint32_t n, uint32_t B, uint32_t cols, uint32_t phase_max, uint32_t teams,
+                PhaseShape *out) {
     if (cols == 0 || phase_max == 0) return false;
+    if (teams != 2 && teams != 4) return false;
     const uint64_t reach = static_cast<uint64_t>(n + 1) * phase_max;
     const uint64_t hb = (reach + B - 1) / B;
     if (cols <= 2 * hb) return false;
     if (cols > 256) return false;
     const uint32_t ldw = (cols + 3u) | 1u;  // three spare columns, odd pitch
     if (pcpd::phase_lds_bytes(B, ldw, phase_max) > pcpd::kMaxLdsBytes) return false;
+    const uint32_t threads = teams * ((cols + 63u) / 64u * 64u);  // one lane per block per team
+    if (threads > 1024) return false;
     out->cols = cols;
-    out->threads = 2u * ((cols + 63u) / 64u * 64u);  // two teams of one lane per block
+    out->threads = threads;
     out->ldw = ldw;
     out->hb = static_cast<uint32_t>(hb);
+    out->teams = teams;
     return true;
 }
+
+// Teams per tile of the default shape.
+constexpr uint32_t kDefaultTeams = 2;
 
 // Default shape: phases of two Monte Carlo steps (at most 128 substeps) and
 // the widest tile of at most 128 blocks that lets two workgroups share a CU
@@ -145,7 +153,7 @@ bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_ma
     for (; pm >= 1; pm = pm / 2) {
         for (uint32_t lds_cap : {pcpd::kMaxLdsBytes / 2, pcpd::kMaxLdsBytes}) {
             for (uint32_t cols = 128; cols >= 1; --cols) {
-                if (make_shape(n, B, cols, pm, shape) &&
+                if (make_shape(n, B, cols, pm, kDefaultTeams, shape) &&
                     pcpd::phase_lds_bytes(B, shape->ldw, pm) <= lds_cap) {
                     *phase_max = pm;
                     return true;
@@ -487,8 +495,10 @@ hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t
     const uint32_t pm_list[] = {B / 2, B, 2 * B, 3 * B, 4 * B};
     for (uint32_t cols : cols_list) {
         for (uint32_t pm : pm_list) {
+          for (uint32_t teams : {2u, 4u}) {
             PhaseShape sh{};
-            if (pm == 0 || pm > 512 || !make_shape(static_cast<uint32_t>(ctx->n), B, cols, pm, &sh))
+            if (pm == 0 || pm > 512 ||
+                !make_shape(static_cast<uint32_t>(ctx->n), B, cols, pm, teams, &sh))
                 continue;
             ctx->shape = sh;
             ctx->phase_max = pm;
@@ -512,6 +522,8 @@ hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t
                 *best_pm = pm;
                 found = true;
             }
+          }
+          if (e != hipSuccess) break;
         }
         if (e != hipSuccess) break;
     }
@@ -767,13 +779,14 @@ int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning) {
     if (ctx->broken) return PCPD_ESTATE;
     PhaseShape shape{};
     uint32_t pmax = ctx->phase_max;
-    if (tuning->tile_cols == 0 && tuning->phase_max == 0) {
+    if (tuning->tile_cols == 0 && tuning->phase_max == 0 && tuning->teams == 0) {
         if (!default_shape(static_cast<uint32_t>(ctx->n), ctx->B, &shape, &pmax))
             return PCPD_EINVAL;
     } else {
         pmax = tuning->phase_max ? tuning->phase_max : ctx->phase_max;
         const uint32_t cols = tuning->tile_cols ? tuning->tile_cols : ctx->shape.cols;
-        if (!make_shape(static_cast<uint32_t>(ctx->n), ctx->B, cols, pmax, &shape))
+        const uint32_t teams = tuning->teams ? tuning->teams : ctx->shape.teams;
+        if (!make_shape(static_cast<uint32_t>(ctx->n), ctx->B, cols, pmax, teams, &shape))
             return PCPD_EINVAL;
     }
     // tiles in flight must not see their table change
@@ -788,6 +801,7 @@ int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
     if (!ctx || !tuning) return PCPD_EINVAL;
     tuning->tile_cols = ctx->shape.cols;
     tuning->phase_max = ctx->phase_max;
+    tuning->teams = ctx->shape.teams;
     return PCPD_OK;
 }
 
@@ -823,6 +837,7 @@ int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen) {
     if (chosen) {
         chosen->tile_cols = best.cols;
         chosen->phase_max = best_pm;
+        chosen->teams = best.teams;
     }
     return PCPD_OK;
 }

@@ -52,9 +52,10 @@ constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
 // Kernel shape of one phase launch.
 struct PhaseShape {
     uint32_t cols;     // blocks held in LDS per workgroup (interior + 2*halo)
-    uint32_t threads;  // workgroup size: two teams of a multiple of 64 >= cols lanes
+    uint32_t threads;  // workgroup size: `teams` teams of a multiple of 64 >= cols lanes
     uint32_t ldw;      // LDS row pitch in words (>= cols + 3, odd)
     uint32_t hb;       // halo blocks on each side
+    uint32_t teams;    // lanes per block (2 or 4), each applying every teams-th substep
 };
 
 // One phase: S substeps starting at substep *clock + s_off.

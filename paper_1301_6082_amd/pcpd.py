@@ -47,7 +47,7 @@ class CountsC(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_cols", u32), ("phase_max", u32)]
+    _fields_ = [("tile_cols", u32), ("phase_max", u32), ("teams", u32)]
 
 
 EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcpd_run",
@@ -216,14 +216,15 @@ class Sim:
         _check(_lib.pcpd_time(self._ctx, ctypes.byref(t)), "pcpd_time")
         return int(t.value)
 
-    def set_tuning(self, tile_cols: int = 0, phase_max: int = 0):
-        tu = Tuning(int(tile_cols), int(phase_max))
+    def set_tuning(self, tile_cols: int = 0, phase_max: int = 0, teams: int = 0):
+        """All 0: the default shape; otherwise a 0 keeps the current value."""
+        tu = Tuning(int(tile_cols), int(phase_max), int(teams))
         _check(_lib.pcpd_set_tuning(self._ctx, ctypes.byref(tu)), "pcpd_set_tuning")
 
     def get_tuning(self):
         tu = Tuning()
         _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
-        return int(tu.tile_cols), int(tu.phase_max)
+        return int(tu.tile_cols), int(tu.phase_max), int(tu.teams)
 
     def set_options(self, graph: bool = False):
         """graph=True: capture each sweep/run batch into a HIP graph and replay it."""
@@ -233,7 +234,7 @@ class Sim:
         """Time candidate tile shapes on this lattice (state unchanged); returns the choice."""
         tu = Tuning()
         _check(_lib.pcpd_autotune(self._ctx, int(reps), ctypes.byref(tu)), "pcpd_autotune")
-        return int(tu.tile_cols), int(tu.phase_max)
+        return int(tu.tile_cols), int(tu.phase_max), int(tu.teams)
 
     def profile(self, enable: bool = True):
         """Bracket every phase-kernel launch with HIP events on the stream."""

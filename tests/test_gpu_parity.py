@@ -53,39 +53,46 @@ def test_cfg1_full_parity(pcpd):
 
 
 def test_several_tiles_and_ragged_tail(pcpd):
-    # 537 blocks: two full 250-block tiles and a ragged 37-block tile per plane
+    # 537 blocks: four full 116-block tiles and a ragged 73-block tile per plane
     insts = [Instance(0.13, 0.3, 64 * 537, 0), Instance(0.2, 0.7, 64 * 300, 5)]
     _compare_full(pcpd, 2, 64, 2, 7, insts, [0, 1, 3, 12])
 
 
+@pytest.mark.parametrize("teams", [2, 4])
 @pytest.mark.parametrize("model", [1, 3, 4])
-def test_dp_tcpd_qcpd_parity(pcpd, model):
+def test_dp_tcpd_qcpd_parity(pcpd, model, teams):
     insts = [Instance(0.08, 0.5, 64 * 260, 1), Instance(0.3, 0.1, 64 * 17, 2)]
-    _compare_full(pcpd, model, 64, 1, 3, insts, [2, 9])
+    _compare_full(pcpd, model, 64, 1, 3, insts, [2, 9], tuning=(0, 0, teams))
 
 
-@pytest.mark.parametrize("tuning", [(256, 64), (128, 64), (64, 16), (9, 1), (40, 7), (200, 33)])
-def test_tile_shape_does_not_change_results(pcpd, tuning):
+@pytest.mark.parametrize("teams", [2, 4])
+@pytest.mark.parametrize("shape", [(256, 64), (128, 64), (64, 16), (9, 1), (40, 7), (200, 33),
+                                   (128, 128), (96, 61)])
+def test_tile_shape_does_not_change_results(pcpd, shape, teams):
+    """Tile width, phase length (including phases that end inside a group of
+    substeps) and team count never change the results."""
     insts = [Instance(0.12, 0.4, 64 * 301, 3)]
-    _compare_full(pcpd, 2, 64, 1, 11, insts, [4], tuning=tuning)
+    _compare_full(pcpd, 2, 64, 1, 11, insts, [4], tuning=(*shape, teams))
 
 
+@pytest.mark.parametrize("teams", [2, 4])
 @pytest.mark.parametrize("L,B,model", [(4, 4, 2), (5, 5, 2), (8, 4, 2), (6, 6, 3), (3, 3, 1),
                                        (192, 192, 2), (96, 32, 2), (1000, 8, 2), (6, 6, 4),
                                        (7, 7, 4), (12, 6, 4), (1200, 12, 4)])
-def test_small_rings_and_block_widths(pcpd, L, B, model):
+def test_small_rings_and_block_widths(pcpd, L, B, model, teams):
     insts = [Instance(0.2, 0.3, L, 0), Instance(0.05, 0.9, L, 1)]
-    _compare_full(pcpd, model, B, 2, 1, insts, [1, 2, 17])
+    _compare_full(pcpd, model, B, 2, 1, insts, [1, 2, 17], tuning=(0, 0, teams))
 
 
+@pytest.mark.parametrize("teams", [2, 4])
 @pytest.mark.parametrize("L,B,model", [(32 * 700, 32, 2), (96 * 150, 96, 2), (16 * 1500, 16, 3),
                                        (64 * 700, 64, 1), (15 * 1400, 15, 2), (9 * 2000, 9, 3),
                                        (64 * 700, 64, 4), (11 * 1800, 11, 4)])
-def test_block_widths_over_many_tiles(pcpd, L, B, model):
+def test_block_widths_over_many_tiles(pcpd, L, B, model, teams):
     """Block widths other than 64 over many tiles per ring: even widths move
     tiles as 16-byte site pairs, odd widths one word at a time."""
     insts = [Instance(0.15, 0.4, L, 5), Instance(0.1, 0.7, L + 2 * B, 6)]
-    _compare_full(pcpd, model, B, 2, 4, insts, [3, 10])
+    _compare_full(pcpd, model, B, 2, 4, insts, [3, 10], tuning=(0, 0, teams))
 
 
 def test_host_init_resume_and_chunking(pcpd):
