@@ -61,6 +61,8 @@ def parse():
                     help="time the library's tile shapes on the workload first (untimed)")
     ap.add_argument("--teams", type=int, default=0, choices=(0, 2, 4),
                     help="lanes per block of the phase kernel (0 = the library's default)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="all phases between records in one ticket-dispatched launch")
     return ap.parse_args()
 
 
@@ -144,6 +146,8 @@ def main():
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
     if args.teams:
         sim.set_tuning(0, 0, args.teams)
+    if args.persistent:
+        sim.set_options(persistent=True)
     if args.autotune:
         sim.autotune()
 
@@ -202,7 +206,7 @@ def main():
     config.update({"mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
                    "records": "the workload's log-spaced record times, plus each step end",
                    "tile_cols": tuning[0], "phase_max": tuning[1], "teams": tuning[2],
-                   "autotuned": args.autotune})
+                   "persistent": args.persistent, "autotuned": args.autotune})
 
     out = {
         "metric": "site-updates/sec (samples x sites x MC steps) at 1 GPU",
@@ -221,6 +225,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)",
                      "frac": achieved / PEAK_SLOTS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": f"brs_phase<{wl.model}>", "launch_ms": launch_ms,
                      "launches": launches, "ops_per_word_update": ops_word,
                      "site_updates_per_s_at_peak": PEAK_SLOTS / ops_word * 64,

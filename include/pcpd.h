@@ -184,12 +184,20 @@ PCPD_API int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning);
 
 /* Options of a context (bit flags). */
 typedef enum {
-    PCPD_OPT_GRAPH = 1  /* run the sweeps of pcpd_sweep / pcpd_run in segments of a fixed
-                           number of Monte Carlo steps (256 phase launches), each captured into
-                           a HIP graph on first use and replayed whenever a segment comes again
-                           (same copy parity); the kernels read the substep index from a device
-                           clock, so a replay is valid at any starting time. Remainders and
-                           density records are launched directly. Ignored while profiling. */
+    /* Run the sweeps of pcpd_sweep / pcpd_run in segments of a fixed number of Monte Carlo
+     * steps (256 phase launches), each captured into a HIP graph on first use and replayed
+     * whenever a segment comes again (same copy parity); the kernels read the substep index
+     * from a device clock, so a replay is valid at any starting time. Remainders and density
+     * records are launched directly. Ignored while profiling. */
+    PCPD_OPT_GRAPH = 1,
+    /* Run all phases between two records in one launch of resident workgroups that take work
+     * items (phase, tile) in order from an atomic ticket; an item starts once the tiles it
+     * reads from have finished the previous phase (per-tile completion flags), so phases
+     * overlap and no launch boundary separates them (paper Sec. 3: more independent systems
+     * and more tiles than one phase fills). Results are identical. A dependency wait that
+     * exceeds its bound (a correct run never does) stops the launch; the next synchronising
+     * call returns PCPD_EDEVICE. With PCPD_OPT_GRAPH the persistent launches are captured. */
+    PCPD_OPT_PERSISTENT = 2
 } pcpd_option;
 
 PCPD_API int pcpd_set_options(pcpd_ctx *ctx, uint32_t options);
@@ -252,6 +260,11 @@ PCPD_API int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst,
 
 /* Release the context and everything the library allocated for it. */
 PCPD_API int pcpd_free(pcpd_ctx *ctx);
+
+/* Description of the HIP failure behind the context's last PCPD_EDEVICE or
+ * PCPD_ENOMEM ("none" if there was none); static storage, valid until the
+ * library is unloaded. */
+PCPD_API const char *pcpd_device_error(pcpd_ctx *ctx);
 
 /* Static description of a status code. */
 PCPD_API const char *pcpd_strerror(int status);

@@ -592,25 +592,16 @@ __device__ __forceinline__ void store_interior_pairs(uint64_t *__restrict__ out,
 // LDS row pitch of the default tile (128 columns plus three spare, odd).
 constexpr uint32_t kDefaultPitch = 131;
 
-// One workgroup per tile, T lanes per block (the T teams). With 128-block
-// tiles two workgroups share a CU, with 256-block tiles one does: T
-// wavefronts per SIMD. PITCH is the LDS row pitch as a compile-time constant
-// (0: the ldw_arg argument); with a constant pitch the rows of a window are
-// immediate offsets from one address.
+// One tile for one phase: load the tile and its halo from `src` into LDS,
+// run S substeps starting at substep s0, write the interior to `dst`. T
+// lanes per block (the T teams).
 template <int N, uint32_t PITCH, int T>
-__global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
-brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
-          const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
-          const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
-          uint32_t cols, uint32_t ldw_arg) {
+__device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__restrict__ src,
+                                           uint64_t *__restrict__ dst, const LatDesc &ld,
+                                           const TileDesc &td, uint64_t s0, uint32_t S,
+                                           uint32_t B, uint32_t hb, uint32_t cols,
+                                           uint32_t ldw_arg) {
     const uint32_t ldw = PITCH ? PITCH : ldw_arg;
-    // first substep of the phase: the context's device clock plus this
-    // launch's offset, so that a captured sequence of launches is valid at
-    // any starting time
-    const uint64_t s0 = *clock + s_off;
-    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
-    const TileDesc td = tiles[blockIdx.x];
-    const LatDesc ld = lats[td.lat];
     const uint32_t nb = ld.nblocks;
     const uint32_t ncols = td.kint + 2u * hb;
     const uint32_t tid = threadIdx.x;
@@ -663,6 +654,156 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
         store_interior(out, lds, hb, td.kint * B, B, ldw, tid, nthr);
 }
 
+// One workgroup per tile, one phase per launch. With 128-block tiles two
+// workgroups share a CU, with 256-block tiles one does: T wavefronts per
+// SIMD. PITCH is the LDS row pitch as a compile-time constant (0: the ldw_arg
+// argument); with a constant pitch the rows of a window are immediate offsets
+// from one address.
+template <int N, uint32_t PITCH, int T>
+__global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
+brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
+          const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
+          const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
+          uint32_t cols, uint32_t ldw_arg) {
+    // first substep of the phase: the context's device clock plus this
+    // launch's offset, so that a captured sequence of launches is valid at
+    // any starting time
+    const uint64_t s0 = *clock + s_off;
+    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
+    const TileDesc td = tiles[blockIdx.x];
+    const LatDesc ld = lats[td.lat];
+    tile_phase<N, PITCH, T>(lds, src, dst, ld, td, s0, S, B, hb, cols, ldw_arg);
+}
+
+// ---- persistent sweep: every phase of a stretch in one launch --------------
+//
+// Work items (phase f, tile k) are handed out in order by an atomic ticket,
+// phase-major, to a grid of resident workgroups, each of which loops until the
+// tickets run out. Item (f, k) reads copy f % 2 and writes copy (f + 1) % 2.
+// Before it starts it waits until every tile j in deps(k) -- the tiles whose
+// interiors meet tile k's loaded range, which are also the tiles whose loaded
+// ranges meet tile k's interior -- has finished phase f - 1: then what it
+// reads is written (phase f - 1 of those tiles) and what it overwrites (tile
+// k's interior in copy (f + 1) % 2) is no longer read (phase f - 1 of those
+// tiles read it). Items only wait on items with smaller tickets, which were
+// taken by running workgroups, so the oldest unfinished item can always
+// proceed. Results are those of one launch per phase.
+//
+// Completion flags count finished phases per tile. Every wavefront of a
+// finished item waits for its stores to reach the L2; after a barrier, one
+// lane releases at agent scope (the L2 written back, visible to other XCDs)
+// and sets the flag. Wavefront 0 of a waiting item polls the flags and then
+// acquires at agent scope (L1 and L2 invalidated) before a barrier releases
+// the workgroup to load the tile. One release and one acquire per item: with
+// one per wavefront the L2 write-backs cost half the sweep's rate. A wait
+// is bounded: past `spin_limit` polls the launch sets *abort and every
+// workgroup stops (the host reports a device error); a correct schedule never
+// comes near the limit.
+
+template <int N, uint32_t PITCH, int T>
+__global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
+brs_persistent(uint64_t *__restrict__ buf0, uint64_t *__restrict__ buf1,
+               const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
+               const TileDeps *__restrict__ deps, uint32_t ntiles, uint32_t nphases,
+               const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t S_last,
+               uint32_t B, uint32_t hb, uint32_t cols, uint32_t ldw_arg,
+               PersistState *__restrict__ state, uint32_t *__restrict__ done,
+               uint32_t spin_limit) {
+    extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
+    __shared__ uint32_t sh_item, sh_stop;
+    const uint64_t clk = *clock;
+    const uint32_t tid = threadIdx.x;
+    const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64u;  // uniform per wavefront
+    const uint32_t items = ntiles * nphases;
+    uint32_t prev = items;  // the item finished last, not yet published (none)
+    for (;;) {
+        // One lane publishes the item just finished (every wavefront released
+        // its stores at agent scope before the barrier that ended the item)
+        // and takes the next ticket. No barrier and no loop inside this
+        // branch: it is the only code that depends on the lane.
+        if (tid == 0) {
+            if (prev < items) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(done + (prev % ntiles), prev / ntiles + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            uint32_t t = __hip_atomic_fetch_add(&state->ticket, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_load(&state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                t = items;
+            sh_item = t;
+        }
+        __syncthreads();
+        // every wavefront reads the same word: they all leave together
+        const uint32_t t = __builtin_amdgcn_readfirstlane(sh_item);
+        if (t >= items) break;
+        const uint32_t f = t / ntiles, k = t - f * ntiles;
+        if (wave0) {
+          bool ok = true;
+          if (f > 0u) {
+            // wavefront 0 waits for phase f - 1 of the tiles k depends on:
+            // deps(k) are the tiles local - lo .. local + hi of k's ring
+            // (cyclic), or all of them when that span covers the ring
+            const TileDeps dp = deps[k];
+            const uint32_t lo = dp.lohi & 0xFFFFu, hi = dp.lohi >> 16;
+            const uint32_t span = lo + hi + 1u;
+            const bool all = span >= dp.count;
+            const uint32_t nd = all ? dp.count : span;
+            const uint32_t j0 = all ? 0u : dp.local + dp.count - lo;  // lo < count here
+            uint32_t polls = 0;
+            for (uint32_t d = 0; d < nd && ok; ++d) {
+                const uint32_t *flag = done + dp.first + (j0 + d) % dp.count;
+                while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                           flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < f) {
+                    if (++polls > spin_limit ||
+                        __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            &state->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                        __hip_atomic_store(&state->abort, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+            }
+            // one agent-scope acquire invalidates the CU's L1 and the XCD's L2
+            // for every wavefront of the workgroup; it has completed before
+            // the barrier below, so no later load of the tile sees stale lines
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(0);
+          }
+          sh_stop = ok ? 0u : 1u;  // the same value from every lane of wavefront 0
+        }
+        __syncthreads();  // the whole workgroup waits for wavefront 0's wait
+        if (__builtin_amdgcn_readfirstlane(sh_stop)) break;
+        const TileDesc td = tiles[k];
+        const LatDesc ld = lats[td.lat];
+        const uint64_t s0 = clk + s_off + static_cast<uint64_t>(f) * S;
+        const uint32_t Sf = (f + 1u == nphases) ? S_last : S;
+        tile_phase<N, PITCH, T>(lds, (f & 1u) ? buf1 : buf0, (f & 1u) ? buf0 : buf1, ld, td, s0,
+                                Sf, B, hb, cols, ldw_arg);
+        // Every wavefront waits until its own stores have reached the L2 (a
+        // workgroup barrier alone does not wait for global stores); the lane
+        // that publishes the item then writes the L2 back with one
+        // agent-scope release, which covers the stores of every wavefront.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // all stores in L2; LDS free for the next item
+        prev = t;
+    }
+}
+
+// Clear the ticket, the abort word and the completion flags of a persistent
+// launch (a kernel, not a memset, so that it can be captured in a graph).
+__global__ void persist_reset(PersistState *__restrict__ state, uint32_t *__restrict__ done,
+                              uint32_t ntiles) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        state->ticket = 0u;
+        state->abort = 0u;
+    }
+    for (uint32_t j = i; j < ntiles; j += gridDim.x * blockDim.x) done[j] = 0u;
+}
+
 template <int N, uint32_t PITCH, int T>
 hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
@@ -693,6 +834,66 @@ hipError_t launch_teams(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                                                       S, B, sh, stream);
     }
     return launch_kernel<N, 0, T>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+}
+
+template <int N, uint32_t PITCH, int T>
+hipError_t launch_persist_kernel(const PersistLaunch &a, const PhaseShape &sh,
+                                 hipStream_t stream) {
+    auto kernel = &brs_persistent<N, PITCH, T>;
+    const size_t lds = phase_lds_bytes(a.B, sh.ldw, a.S);
+    if (lds + kPersistStaticLds > kMaxLdsBytes) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        // the kernel's own shared words come out of the same 160 KB
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(kMaxLdsBytes - kPersistStaticLds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    // as many workgroups as are resident at once, at most one per item; the
+    // count bounds only the grid (workgroups that are not resident yet take
+    // no ticket), so the LDS bound stands in if the occupancy query fails
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel),
+                                                     static_cast<int>(sh.threads),
+                                                     lds) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = static_cast<int>(kMaxLdsBytes / (lds + 64));
+    }
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const uint64_t items = static_cast<uint64_t>(a.ntiles) * a.nphases;
+    uint64_t grid = static_cast<uint64_t>(per_cu > 0 ? per_cu : 1) * static_cast<uint64_t>(cus);
+    if (grid > items) grid = items;
+    hipLaunchKernelGGL(persist_reset, dim3((a.ntiles + 255u) / 256u), dim3(256), 0, stream,
+                       a.state, a.done, a.ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(static_cast<uint32_t>(grid)), dim3(sh.threads), lds, stream,
+                       a.buf0, a.buf1, a.lats, a.tiles, a.deps, a.ntiles, a.nphases, a.clock,
+                       a.s_off, a.S, a.S_last, a.B, sh.hb, sh.cols, sh.ldw, a.state, a.done,
+                       a.spin_limit);
+    return hipGetLastError();
+}
+
+template <int N, int T>
+hipError_t launch_persist_teams(const PersistLaunch &a, const PhaseShape &sh, hipStream_t stream) {
+    if constexpr (N == 2) {
+        if (sh.ldw == kDefaultPitch) return launch_persist_kernel<N, kDefaultPitch, T>(a, sh, stream);
+    }
+    return launch_persist_kernel<N, 0, T>(a, sh, stream);
+}
+
+template <int N>
+hipError_t launch_persist_n(const PersistLaunch &a, const PhaseShape &sh, hipStream_t stream) {
+    if (a.ntiles == 0 || a.nphases == 0) return hipSuccess;
+    switch (sh.teams) {
+        case 2: return launch_persist_teams<N, 2>(a, sh, stream);
+        case 4: return launch_persist_teams<N, 4>(a, sh, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // The default PCPD tile runs a copy of the kernel compiled for its pitch;

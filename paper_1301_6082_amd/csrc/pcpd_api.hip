@@ -20,7 +20,10 @@
 using pcpd::Counts;
 using pcpd::DenChunk;
 using pcpd::LatDesc;
+using pcpd::PersistLaunch;
+using pcpd::PersistState;
 using pcpd::PhaseShape;
+using pcpd::TileDeps;
 using pcpd::TileDesc;
 
 static_assert(sizeof(pcpd_counts) == sizeof(Counts), "count layout");
@@ -44,6 +47,10 @@ struct pcpd_ctx {
     LatDesc *d_lats = nullptr;
     TileDesc *d_tiles = nullptr;
     uint32_t ntiles = 0;
+    TileDeps *d_deps = nullptr;      // per tile, for persistent launches
+    uint32_t *d_done = nullptr;      // [ntiles] completion flags of a persistent launch
+    PersistState *d_pstate = nullptr;
+    uint32_t *h_abort = nullptr;     // pinned copy of d_pstate->abort after each batch
     DenChunk *d_chunks = nullptr;
     uint32_t nchunks = 0;
     Counts *d_counts = nullptr;      // [count_slots][nlat]
@@ -56,6 +63,7 @@ struct pcpd_ctx {
 
     uint64_t t = 0;
     bool broken = false;
+    hipError_t last_error = hipSuccess;  // the HIP status behind the last PCPD_EDEVICE / ENOMEM
 
     bool profiling = false;
     std::vector<hipEvent_t> events;  // pairs (start, stop) per profiled launch
@@ -87,6 +95,9 @@ struct pcpd_ctx::GraphEntry {
 namespace {
 
 constexpr uint32_t kDenChunkWords = 8192;
+// Polls of one dependency wait in a persistent launch before it gives up
+// (about a second; a correct schedule waits at most a few item durations).
+constexpr uint32_t kPersistSpinLimit = 1u << 20;
 constexpr size_t kMaxGraphs = 16;
 
 // K = rint(q * 2^34): the integer threshold of a probability-q decision.
@@ -167,12 +178,23 @@ bool default_shape(uint32_t n, uint32_t B, PhaseShape *shape, uint32_t *phase_ma
 
 int fail(pcpd_ctx *ctx, hipError_t e) {
     if (e == hipSuccess) return PCPD_OK;
-    if (ctx) ctx->broken = true;
+    if (ctx) {
+        ctx->broken = true;
+        ctx->last_error = e;
+    }
     return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? PCPD_ENOMEM
                                                                        : PCPD_EDEVICE;
 }
 
 void drop_graphs(pcpd_ctx *ctx);
+
+// Wait for the context's stream; a persistent launch that gave up a wait
+// (its abort word, copied to the host after each batch) is a device error.
+hipError_t sync_checked(pcpd_ctx *ctx) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && ctx->h_abort && *ctx->h_abort) e = hipErrorLaunchTimeOut;
+    return e;
+}
 
 // Tiles of a shape over a set of rings: each ring cut into runs of at most
 // cols - 2*hb interior blocks.
@@ -190,6 +212,36 @@ std::vector<TileDesc> plan_tiles(const std::vector<LatDesc> &lats, const PhaseSh
         }
     }
     return tiles;
+}
+
+// Dependencies of each tile in a persistent launch (TileDeps): going back
+// from a tile, the fewest preceding tiles of its ring whose interiors cover
+// the hb halo blocks (lo), and likewise forward (hi). plan_tiles emits the
+// tiles of a ring consecutively.
+std::vector<TileDeps> plan_deps(const std::vector<TileDesc> &tiles, uint32_t hb) {
+    std::vector<TileDeps> deps(tiles.size());
+    size_t r0 = 0;
+    while (r0 < tiles.size()) {
+        size_t r1 = r0;
+        while (r1 < tiles.size() && tiles[r1].lat == tiles[r0].lat) ++r1;
+        const uint32_t cnt = static_cast<uint32_t>(r1 - r0);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            uint32_t lo = 0, hi = 0;
+            for (uint32_t covered = 0; covered < hb && lo < cnt; ++lo)
+                covered += tiles[r0 + (i + cnt - 1 - lo) % cnt].kint;
+            for (uint32_t covered = 0; covered < hb && hi < cnt; ++hi)
+                covered += tiles[r0 + (i + 1 + hi) % cnt].kint;
+            TileDeps d{};
+            d.first = static_cast<uint32_t>(r0);
+            d.count = cnt;
+            d.local = i;
+            if (lo + hi + 1 >= cnt) lo = hi = cnt;  // the whole ring
+            d.lohi = std::min<uint32_t>(lo, 0xFFFF) | (std::min<uint32_t>(hi, 0xFFFF) << 16);
+            deps[r0 + i] = d;
+        }
+        r0 = r1;
+    }
+    return deps;
 }
 
 // Chunks of the density reduction: every ring cut into runs of kDenChunkWords.
@@ -247,8 +299,18 @@ hipError_t build_tiles(pcpd_ctx *ctx) {
     if (e != hipSuccess) return e;
     e = hipMemcpy(ctx->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc),
                   hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
     ctx->ntiles = static_cast<uint32_t>(tiles.size());
-    return e;
+    // dependencies and completion flags of persistent launches
+    const std::vector<TileDeps> deps = plan_deps(tiles, ctx->shape.hb);
+    if (ctx->d_deps) (void)hipFree(ctx->d_deps);
+    if (ctx->d_done) (void)hipFree(ctx->d_done);
+    ctx->d_deps = nullptr;
+    ctx->d_done = nullptr;
+    if ((e = hipMalloc(&ctx->d_deps, deps.size() * sizeof(TileDeps))) != hipSuccess) return e;
+    if ((e = hipMalloc(&ctx->d_done, deps.size() * sizeof(uint32_t))) != hipSuccess) return e;
+    return hipMemcpy(ctx->d_deps, deps.data(), deps.size() * sizeof(TileDeps),
+                     hipMemcpyHostToDevice);
 }
 
 hipError_t ensure_count_slots(pcpd_ctx *ctx, uint32_t slots) {
@@ -301,8 +363,50 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
                        bool profile, int *cur_out) {
     int cur = ctx->cur;
     uint64_t rel = 0;
+    // shapes whose tile fills the whole LDS leave no room for the persistent
+    // kernel's own words and run one launch per phase
+    const bool persistent =
+        (ctx->options & PCPD_OPT_PERSISTENT) && ctx->d_pstate &&
+        pcpd::phase_lds_bytes(ctx->B, ctx->shape.ldw, ctx->phase_max) + pcpd::kPersistStaticLds <=
+            pcpd::kMaxLdsBytes;
     for (const BatchOp &op : ops) {
         const uint64_t end = rel + op.steps * ctx->B;
+        if (persistent && end > rel) {
+            // every phase of this stretch in one launch
+            const uint64_t sub = end - rel;
+            const uint64_t nph = (sub + ctx->phase_max - 1) / ctx->phase_max;
+            PersistLaunch a{};
+            a.buf0 = ctx->buf[cur];
+            a.buf1 = ctx->buf[cur ^ 1];
+            a.lats = ctx->d_lats;
+            a.tiles = ctx->d_tiles;
+            a.deps = ctx->d_deps;
+            a.ntiles = ctx->ntiles;
+            a.nphases = static_cast<uint32_t>(nph);
+            a.clock = ctx->d_clock;
+            a.s_off = rel;
+            a.S = ctx->phase_max;
+            a.S_last = static_cast<uint32_t>(sub - (nph - 1) * ctx->phase_max);
+            a.B = ctx->B;
+            a.state = ctx->d_pstate;
+            a.done = ctx->d_done;
+            a.spin_limit = kPersistSpinLimit;
+            if (nph >= (1ull << 32) / std::max<uint32_t>(ctx->ntiles, 1)) return hipErrorInvalidValue;
+            hipEvent_t *ev = nullptr;
+            if (profile) {
+                hipError_t e = next_event_pair(ctx, &ev);
+                if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = pcpd::launch_persist(ctx->n, a, ctx->shape, stream);
+            if (e == hipSuccess && ev) e = hipEventRecord(ev[1], stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->h_abort, &ctx->d_pstate->abort, sizeof(uint32_t),
+                                   hipMemcpyDeviceToHost, stream);
+            if (e != hipSuccess) return e;
+            if (nph & 1) cur ^= 1;
+            rel = end;
+        }
         while (rel < end) {
             const uint32_t S = static_cast<uint32_t>(std::min<uint64_t>(ctx->phase_max, end - rel));
             hipEvent_t *ev = nullptr;
@@ -433,6 +537,10 @@ void release(pcpd_ctx *ctx) {
     if (ctx->owns_buf && ctx->buf[0]) (void)hipFree(ctx->buf[0]);
     if (ctx->d_lats) (void)hipFree(ctx->d_lats);
     if (ctx->d_tiles) (void)hipFree(ctx->d_tiles);
+    if (ctx->d_deps) (void)hipFree(ctx->d_deps);
+    if (ctx->d_done) (void)hipFree(ctx->d_done);
+    if (ctx->d_pstate) (void)hipFree(ctx->d_pstate);
+    if (ctx->h_abort) (void)hipHostFree(ctx->h_abort);
     if (ctx->d_chunks) (void)hipFree(ctx->d_chunks);
     if (ctx->d_counts) (void)hipFree(ctx->d_counts);
     if (ctx->h_counts) (void)hipHostFree(ctx->h_counts);
@@ -663,10 +771,13 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
         (e = hipMemcpy(ctx->d_chunks, chunks.data(), chunks.size() * sizeof(DenChunk),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = build_tiles(ctx)) != hipSuccess || (e = ensure_count_slots(ctx, 1)) != hipSuccess ||
-        (e = hipMalloc(&ctx->d_clock, sizeof(uint64_t))) != hipSuccess) {
+        (e = hipMalloc(&ctx->d_clock, sizeof(uint64_t))) != hipSuccess ||
+        (e = hipMalloc(&ctx->d_pstate, sizeof(PersistState))) != hipSuccess ||
+        (e = hipHostMalloc(&ctx->h_abort, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) {
         release(ctx);
         return fail(nullptr, e);
     }
+    *ctx->h_abort = 0;
     const uint64_t sub0 = t0 * cfg->B;
     e = hipMemcpy(ctx->d_clock, &sub0, sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -710,7 +821,7 @@ int pcpd_density(pcpd_ctx *ctx, pcpd_counts *out) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts, ctx->nlat * sizeof(Counts),
                            hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);
     std::memcpy(out, ctx->h_counts, ctx->nlat * sizeof(Counts));
     return PCPD_OK;
@@ -735,7 +846,7 @@ int pcpd_run(pcpd_ctx *ctx, const uint64_t *times, uint32_t n_times, pcpd_counts
         e = hipMemcpyAsync(ctx->h_counts, ctx->d_counts,
                            static_cast<size_t>(n_times) * ctx->nlat * sizeof(Counts),
                            hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);
     if (n_times)
         std::memcpy(out, ctx->h_counts, static_cast<size_t>(n_times) * ctx->nlat * sizeof(Counts));
@@ -748,7 +859,7 @@ int pcpd_get_lattice(pcpd_ctx *ctx, uint32_t inst, uint64_t *host_words) {
     const size_t bytes = ctx->L[inst] * ctx->planes * sizeof(uint64_t);
     hipError_t e = hipMemcpyAsync(host_words, ctx->buf[ctx->cur] + ctx->inst_base[inst], bytes,
                                   hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = sync_checked(ctx);
     return fail(ctx, e);
 }
 
@@ -758,7 +869,7 @@ int pcpd_set_lattice(pcpd_ctx *ctx, uint32_t inst, const uint64_t *host_words) {
     const size_t bytes = ctx->L[inst] * ctx->planes * sizeof(uint64_t);
     hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur] + ctx->inst_base[inst], host_words, bytes,
                                   hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = sync_checked(ctx);
     return fail(ctx, e);
 }
 
@@ -771,7 +882,7 @@ int pcpd_time(pcpd_ctx *ctx, uint64_t *t_out) {
 int pcpd_sync(pcpd_ctx *ctx) {
     if (!ctx) return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
-    return fail(ctx, hipStreamSynchronize(ctx->stream));
+    return fail(ctx, sync_checked(ctx));
 }
 
 int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning) {
@@ -790,7 +901,7 @@ int pcpd_set_tuning(pcpd_ctx *ctx, const pcpd_tuning *tuning) {
             return PCPD_EINVAL;
     }
     // tiles in flight must not see their table change
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    hipError_t e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);
     ctx->shape = shape;
     ctx->phase_max = pmax;
@@ -806,7 +917,8 @@ int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
 }
 
 int pcpd_set_options(pcpd_ctx *ctx, uint32_t options) {
-    if (!ctx || (options & ~static_cast<uint32_t>(PCPD_OPT_GRAPH))) return PCPD_EINVAL;
+    if (!ctx || (options & ~static_cast<uint32_t>(PCPD_OPT_GRAPH | PCPD_OPT_PERSISTENT)))
+        return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
     ctx->options = options;
     return PCPD_OK;
@@ -828,7 +940,7 @@ int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen) {
         if (e != hipSuccess) return fail(ctx, e);
         tune_cache()[key] = {best, best_pm};
     }
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    hipError_t e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);
     ctx->shape = best;
     ctx->phase_max = best_pm;
@@ -852,7 +964,7 @@ int pcpd_profile(pcpd_ctx *ctx, int enable) {
 int pcpd_profile_read(pcpd_ctx *ctx, double *kernel_ms, uint64_t *launches) {
     if (!ctx || !kernel_ms || !launches) return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    hipError_t e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);
     double total = 0.0;
     for (size_t i = 0; i + 1 < ctx->events_used; i += 2) {
@@ -958,6 +1070,13 @@ int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t
     const hipError_t es = hipStreamSynchronize(stream);
     if (e == hipSuccess) e = es;
     return fail(nullptr, e);
+}
+
+const char *pcpd_device_error(pcpd_ctx *ctx) {
+    if (!ctx) return "no context";
+    if (ctx->last_error == hipErrorLaunchTimeOut && ctx->h_abort && *ctx->h_abort)
+        return "a persistent launch stopped: a dependency wait exceeded its bound";
+    return ctx->last_error == hipSuccess ? "none" : hipGetErrorString(ctx->last_error);
 }
 
 const char *pcpd_strerror(int status) {

@@ -32,6 +32,39 @@ struct TileDesc {
     uint32_t pad;
 };
 
+// The tiles a tile's phase depends on in a persistent launch: the tiles
+// local - lo .. local + hi (cyclic) of its ring, whose tiles are
+// first .. first + count - 1; all of them when lo + hi + 1 >= count.
+struct TileDeps {
+    uint32_t first;  // index of the ring's first tile in the tile table
+    uint32_t count;  // tiles of the ring
+    uint32_t local;  // this tile's index within the ring
+    uint32_t lohi;   // lo | hi << 16
+};
+
+// Ticket counter and abort word of a persistent launch.
+struct PersistState {
+    uint32_t ticket;
+    uint32_t abort;
+};
+
+// One persistent launch: phases 0 .. nphases-1 of S substeps (the last one
+// S_last) starting at substep *clock + s_off; phase f reads buf0 if f is even
+// (buf1 if odd) and writes the other copy.
+struct PersistLaunch {
+    uint64_t *buf0, *buf1;
+    const LatDesc *lats;
+    const TileDesc *tiles;
+    const TileDeps *deps;
+    uint32_t ntiles, nphases;
+    const uint64_t *clock;
+    uint64_t s_off;
+    uint32_t S, S_last, B;
+    PersistState *state;
+    uint32_t *done;      // [ntiles] completed phases per tile
+    uint32_t spin_limit; // polls of one wait before the launch gives up
+};
+
 // One workgroup's share of a density reduction: words [w0, w0 + nw) of `lat`.
 struct DenChunk {
     uint32_t lat;
@@ -48,6 +81,9 @@ struct Counts {
 
 // Largest LDS allocation of one workgroup on gfx950.
 constexpr uint32_t kMaxLdsBytes = 160u * 1024u;
+// Statically allocated LDS of the persistent phase kernel (its item words),
+// which the tile's dynamic LDS must leave free.
+constexpr uint32_t kPersistStaticLds = 64u;
 
 // Kernel shape of one phase launch.
 struct PhaseShape {
@@ -75,6 +111,13 @@ PCPD_PHASE_LAUNCHER(launch_phase_model2);
 PCPD_PHASE_LAUNCHER(launch_phase_model3);
 PCPD_PHASE_LAUNCHER(launch_phase_model4);
 #undef PCPD_PHASE_LAUNCHER
+
+// The persistent launch of one model (n = 1..4).
+hipError_t launch_persist_model1(const PersistLaunch &a, const PhaseShape &shape, hipStream_t stream);
+hipError_t launch_persist_model2(const PersistLaunch &a, const PhaseShape &shape, hipStream_t stream);
+hipError_t launch_persist_model3(const PersistLaunch &a, const PhaseShape &shape, hipStream_t stream);
+hipError_t launch_persist_model4(const PersistLaunch &a, const PhaseShape &shape, hipStream_t stream);
+hipError_t launch_persist(int n, const PersistLaunch &a, const PhaseShape &shape, hipStream_t stream);
 
 // *clock += delta, on the device.
 hipError_t launch_advance_clock(uint64_t *clock, uint64_t delta, hipStream_t stream);

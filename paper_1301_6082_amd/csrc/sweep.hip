@@ -83,6 +83,17 @@ hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc
     }
 }
 
+hipError_t launch_persist(int n, const PersistLaunch &a, const PhaseShape &shape,
+                          hipStream_t stream) {
+    switch (n) {
+        case 1: return launch_persist_model1(a, shape, stream);
+        case 2: return launch_persist_model2(a, shape, stream);
+        case 3: return launch_persist_model3(a, shape, stream);
+        case 4: return launch_persist_model4(a, shape, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_advance_clock(uint64_t *clock, uint64_t delta, hipStream_t stream) {
     hipLaunchKernelGGL(advance_clock, dim3(1), dim3(64), 0, stream, clock, delta);
     return hipGetLastError();

@@ -18,7 +18,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpcpd.so")
 
-OPT_GRAPH = 1
+OPT_GRAPH, OPT_PERSISTENT = 1, 2
 PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
 PCPD_ELIMIT = -6
 NOALLOC_MAX_WORDS = 1 << 22
@@ -54,7 +54,7 @@ EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcp
            "pcpd_get_lattice", "pcpd_set_lattice", "pcpd_time", "pcpd_sync",
            "pcpd_set_tuning", "pcpd_get_tuning", "pcpd_set_options", "pcpd_autotune",
            "pcpd_profile", "pcpd_profile_read", "pcpd_run_noalloc",
-           "pcpd_free", "pcpd_strerror"]
+           "pcpd_device_error", "pcpd_free", "pcpd_strerror"]
 MLP_EXPORTS = ["pcpd_mlp_init", "pcpd_mlp_get_params", "pcpd_mlp_set_params", "pcpd_mlp_predict",
                "pcpd_mlp_grads", "pcpd_mlp_train_step", "pcpd_mlp_free"]
 MLP_PARAMS = 33665
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
                              ctypes.c_int),
         "pcpd_free": ([vp], ctypes.c_int),
         "pcpd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "pcpd_device_error": ([vp], ctypes.c_char_p),
         "pcpd_mlp_init": ([P(vp), u32, P(Device)], ctypes.c_int),
         "pcpd_mlp_get_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_set_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
@@ -105,14 +106,18 @@ _lib = load_library()
 
 
 class PcpdError(RuntimeError):
-    def __init__(self, status: int, where: str):
+    def __init__(self, status: int, where: str, detail: str = ""):
         self.status = status
-        super().__init__(f"{where}: {_lib.pcpd_strerror(status).decode()} ({status})")
+        extra = f" [{detail}]" if detail else ""
+        super().__init__(f"{where}: {_lib.pcpd_strerror(status).decode()} ({status}){extra}")
 
 
-def _check(status: int, where: str):
+def _check(status: int, where: str, ctx=None):
     if status != PCPD_OK:
-        raise PcpdError(status, where)
+        detail = ""
+        if ctx is not None and status in (PCPD_EDEVICE, PCPD_ENOMEM):
+            detail = _lib.pcpd_device_error(ctx).decode()
+        raise PcpdError(status, where, detail)
 
 
 def _u64p(a: np.ndarray):
@@ -180,35 +185,35 @@ class Sim:
 
     # -- stepping and observables
     def sweep(self, n_steps: int):
-        _check(_lib.pcpd_sweep(self._ctx, int(n_steps)), "pcpd_sweep")
+        _check(_lib.pcpd_sweep(self._ctx, int(n_steps)), "pcpd_sweep", self._ctx)
 
     def sync(self):
-        _check(_lib.pcpd_sync(self._ctx), "pcpd_sync")
+        _check(_lib.pcpd_sync(self._ctx), "pcpd_sync", self._ctx)
 
     def density(self) -> np.ndarray:
         """uint64 [n_inst, planes, 3] = (N, N_pair, alive)."""
         out = (CountsC * (self.n_inst * self.planes))()
-        _check(_lib.pcpd_density(self._ctx, out), "pcpd_density")
+        _check(_lib.pcpd_density(self._ctx, out), "pcpd_density", self._ctx)
         return np.frombuffer(out, dtype=np.uint64).reshape(self.n_inst, self.planes, 3).copy()
 
     def run(self, times: Sequence[int]) -> np.ndarray:
         """uint64 [n_times, n_inst, planes, 3] at each record time."""
         t = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
         out = (CountsC * (len(t) * self.n_inst * self.planes))()
-        _check(_lib.pcpd_run(self._ctx, _u64p(t), len(t), out), "pcpd_run")
+        _check(_lib.pcpd_run(self._ctx, _u64p(t), len(t), out), "pcpd_run", self._ctx)
         return np.frombuffer(out, dtype=np.uint64).reshape(len(t), self.n_inst, self.planes, 3).copy()
 
     # -- state
     def get_lattice(self, inst: int) -> np.ndarray:
         w = np.empty(self.planes * self.Ls[inst], dtype=np.uint64)
-        _check(_lib.pcpd_get_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_get_lattice")
+        _check(_lib.pcpd_get_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_get_lattice", self._ctx)
         return w
 
     def set_lattice(self, inst: int, words) -> None:
         w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
         if w.shape != (self.planes * self.Ls[inst],):
             raise ValueError("set_lattice needs planes*L words")
-        _check(_lib.pcpd_set_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_set_lattice")
+        _check(_lib.pcpd_set_lattice(self._ctx, int(inst), _u64p(w)), "pcpd_set_lattice", self._ctx)
 
     @property
     def time(self) -> int:
@@ -219,32 +224,34 @@ class Sim:
     def set_tuning(self, tile_cols: int = 0, phase_max: int = 0, teams: int = 0):
         """All 0: the default shape; otherwise a 0 keeps the current value."""
         tu = Tuning(int(tile_cols), int(phase_max), int(teams))
-        _check(_lib.pcpd_set_tuning(self._ctx, ctypes.byref(tu)), "pcpd_set_tuning")
+        _check(_lib.pcpd_set_tuning(self._ctx, ctypes.byref(tu)), "pcpd_set_tuning", self._ctx)
 
     def get_tuning(self):
         tu = Tuning()
         _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
         return int(tu.tile_cols), int(tu.phase_max), int(tu.teams)
 
-    def set_options(self, graph: bool = False):
-        """graph=True: capture each sweep/run batch into a HIP graph and replay it."""
-        _check(_lib.pcpd_set_options(self._ctx, OPT_GRAPH if graph else 0), "pcpd_set_options")
+    def set_options(self, graph: bool = False, persistent: bool = False):
+        """graph=True: capture sweep segments into HIP graphs and replay them;
+        persistent=True: all phases between two records in one ticket-dispatched launch."""
+        flags = (OPT_GRAPH if graph else 0) | (OPT_PERSISTENT if persistent else 0)
+        _check(_lib.pcpd_set_options(self._ctx, flags), "pcpd_set_options", self._ctx)
 
     def autotune(self, reps: int = 3):
         """Time candidate tile shapes on this lattice (state unchanged); returns the choice."""
         tu = Tuning()
-        _check(_lib.pcpd_autotune(self._ctx, int(reps), ctypes.byref(tu)), "pcpd_autotune")
+        _check(_lib.pcpd_autotune(self._ctx, int(reps), ctypes.byref(tu)), "pcpd_autotune", self._ctx)
         return int(tu.tile_cols), int(tu.phase_max), int(tu.teams)
 
     def profile(self, enable: bool = True):
         """Bracket every phase-kernel launch with HIP events on the stream."""
-        _check(_lib.pcpd_profile(self._ctx, 1 if enable else 0), "pcpd_profile")
+        _check(_lib.pcpd_profile(self._ctx, 1 if enable else 0), "pcpd_profile", self._ctx)
 
     def profile_read(self):
         """(summed phase-kernel milliseconds, launches) since the last read."""
         ms, n = ctypes.c_double(), u64()
         _check(_lib.pcpd_profile_read(self._ctx, ctypes.byref(ms), ctypes.byref(n)),
-               "pcpd_profile_read")
+               "pcpd_profile_read", self._ctx)
         return float(ms.value), int(n.value)
 
     def close(self):

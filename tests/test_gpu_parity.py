@@ -22,14 +22,17 @@ def pcpd():
     return mod
 
 
-def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t0=0):
+def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t0=0,
+                  options=None):
     """GPU run with records at `times` vs the oracle on every plane, all samples."""
     print(f"[parity] model={model} B={B} planes={planes} n_inst={len(instances)} "
-          f"L={[i.L for i in instances]} times={times[:4]}..{times[-1]} tuning={tuning}",
-          flush=True)
+          f"L={[i.L for i in instances]} times={times[:4]}..{times[-1]} tuning={tuning} "
+          f"options={options}", flush=True)
     with pcpd.Sim(model, B, planes, seed, instances, t0=t0) as sim:
         if tuning:
             sim.set_tuning(*tuning)
+        if options:
+            sim.set_options(**options)
         counts = sim.run(times)
         lat = [sim.get_lattice(i) for i in range(len(instances))]
     keys, runs = oracle_runs(model, B, planes, seed, instances, times, t0=t0)
@@ -305,3 +308,57 @@ def test_batch_in_one_graph_launch_matches_instances_alone(pcpd):
             a = alone.run([5, 40])
             np.testing.assert_array_equal(alone.get_lattice(0), lat[i], err_msg=f"inst {i}")
             np.testing.assert_array_equal(a[:, 0], batch[:, i])
+
+
+# ---- persistent launches ----------------------------------------------------
+
+@pytest.mark.parametrize("teams", [2, 4])
+@pytest.mark.parametrize("shape", [(128, 128), (64, 16), (40, 7), (200, 33), (9, 1)])
+def test_persistent_launch_matches_oracle(pcpd, shape, teams):
+    """All phases between records in one ticket-dispatched launch: rings of
+    many tiles, one tile, and fewer blocks than the halo (every tile depends
+    on every other), with phases that end inside a group of substeps."""
+    insts = [Instance(0.12, 0.4, 64 * 301, 3), Instance(0.2, 0.1, 64 * 7, 4),
+             Instance(0.05, 0.8, 64 * 1200, 5)]
+    _compare_full(pcpd, 2, 64, 2, 11, insts, [0, 1, 4, 13], tuning=(*shape, teams),
+                  options={"persistent": True})
+
+
+@pytest.mark.parametrize("L,B,model", [(64 * 260, 64, 1), (64 * 260, 64, 3), (64 * 260, 64, 4),
+                                       (15 * 1400, 15, 2), (1000, 8, 2), (6, 6, 4)])
+def test_persistent_launch_models_and_block_widths(pcpd, L, B, model):
+    insts = [Instance(0.15, 0.4, L, 5), Instance(0.1, 0.7, L + 2 * B, 6)]
+    _compare_full(pcpd, model, B, 2, 4, insts, [3, 10], options={"persistent": True})
+
+
+def test_persistent_launch_in_graphs_matches_direct(pcpd):
+    """Persistent launches captured in graph segments and replayed, with
+    eager work between replays, against direct per-phase launches."""
+    insts = [Instance(0.1, 0.3, 64 * 200, 0), Instance(0.22, 0.6, 64 * 37, 1)]
+    with pcpd.Sim(2, 64, 2, 4, insts) as g, pcpd.Sim(2, 64, 2, 4, insts) as d:
+        g.set_tuning(128, 4)
+        g.set_options(graph=True, persistent=True)
+        for rep in range(3):
+            t = g.time
+            sched = [t + 20, t + 40, t + 75]
+            cg, cd = g.run(sched), d.run(sched)
+            np.testing.assert_array_equal(cg, cd, err_msg=f"replay {rep}")
+            for i in range(2):
+                np.testing.assert_array_equal(g.get_lattice(i), d.get_lattice(i))
+            if rep == 0:
+                g.sweep(1)
+                d.sweep(1)
+
+
+def test_persistent_cfg3_batch_matches_direct(pcpd):
+    """The 512 uneven rings of the batched workload: persistent launches
+    against per-phase launches, lattices and counts at every record."""
+    c = wl.cfg3()
+    times = [3, 8]
+    with pcpd.Sim(c.model, c.B, c.planes, c.seed, c.instances) as p, \
+            pcpd.Sim(c.model, c.B, c.planes, c.seed, c.instances) as d:
+        p.set_options(persistent=True)
+        cp, cd = p.run(times), d.run(times)
+        np.testing.assert_array_equal(cp, cd)
+        for i in (0, 77, 300, 511):
+            np.testing.assert_array_equal(p.get_lattice(i), d.get_lattice(i), err_msg=f"inst {i}")
