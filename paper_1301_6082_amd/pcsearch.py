@@ -158,6 +158,7 @@ def plain_steps(grid: Grid, lo: int, hi: int):
 
 
 CALIBRATED_PROBES = 4     # probes placed by the calibrated surrogate before midpoints
+LEVEL_STEP = 0.0025       # delta_eff change per grid cell above which the level calibrates
 
 
 def match_index(ys, sim_log10, late) -> int:
@@ -165,6 +166,36 @@ def match_index(ys, sim_log10, late) -> int:
     the late times) to a simulated curve."""
     err = np.mean(np.abs(ys[:, late] - sim_log10[late]), axis=1)
     return int(np.argmin(err))
+
+
+def level_index(levels, level_sim: float, probe: int, lo: int = 0, hi: Optional[int] = None) -> int:
+    """Grid index in [lo, hi] whose predicted delta_eff level (last
+    half-decade) is closest to the simulated one; near-ties (within 1e-3) go
+    to the index nearest the probe. Near p_c the level rises steeply with p
+    (about 0.2 at p_c towards 1/2 in the inactive phase), so it places a
+    simulated run on the network's p axis to about a cell even where the
+    curves themselves are nearly alike."""
+    levels = np.asarray(levels, float)
+    hi = len(levels) - 1 if hi is None else hi
+    lo, hi = max(0, lo), min(len(levels) - 1, hi)
+    idx = np.arange(lo, hi + 1)
+    gap = np.abs(levels[lo:hi + 1] - level_sim)
+    gap = np.where(np.isfinite(gap), gap, np.inf)
+    best = gap.min()
+    if not np.isfinite(best):
+        return probe
+    near = idx[gap <= best + 1e-3]
+    return int(near[np.argmin(np.abs(near - probe))])
+
+
+def predicted_levels(ys, times):
+    """delta_eff over the last half-decade of each predicted log10 rho curve."""
+    ys = np.asarray(ys, float)
+    out = np.full(len(ys), np.nan)
+    for j in range(len(ys)):
+        if np.all(np.isfinite(ys[j])):
+            out[j] = delta_eff_windows(times, 10.0 ** ys[j])[1]
+    return out
 
 
 def restrict_to_domain(ys, cls, grid: Grid, domain=None):
@@ -182,14 +213,19 @@ def restrict_to_domain(ys, cls, grid: Grid, domain=None):
 
 
 def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
-                    calibrated: int = CALIBRATED_PROBES):
+                    calibrated: int = CALIBRATED_PROBES, calibration: str = "level"):
     """Bracket search whose probes the surrogate places. `ys` [grid, times]
     are its log10 rho curves for the whole grid and `cls` their classes; its
     flip f0 is where its last run of inactive predictions inside the bracket
     starts.
-    Each simulated probe calibrates it: the grid index j whose predicted
-    curve best matches the simulated one over the last decade of t is where
-    the surrogate puts that curve, so its flip moves by (probe - j). The next
+    Each simulated probe calibrates it: the grid index j where the surrogate
+    puts the simulated curve, so that its flip moves by (probe - j). j is the
+    index whose predicted curve is closest over the last decade of t
+    (match_index); with calibration="level" (the default), where the
+    predicted delta_eff level of the last half-decade changes by LEVEL_STEP
+    or more per cell, j is instead the index with the closest level
+    (level_index): near and above the flip the level rises steeply with p
+    while the curves just below it are nearly alike. The next
     probe is the calibrated flip, or the point below it when the flip is
     already the upper end of the bracket; when the estimate keeps pressing
     against an end of the bracket the step from that end doubles. Once both
@@ -201,6 +237,7 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
     ys = np.asarray(ys, float)
     cls = np.asarray(cls, bool)
     late = np.asarray(times, float) >= float(times[-1]) / 10.0
+    levels = predicted_levels(ys, times) if calibration == "level" else None
     # the surrogate's flip: the start of its last run of inactive predictions
     # inside the bracket (spurious inactive predictions far below it, e.g.
     # where the network extrapolates, do not count)
@@ -235,13 +272,24 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
         else:
             probe = (lo + hi) // 2
         _, rho, ina = yield probe
+        lo0, hi0 = lo, hi  # the bracket the probe was placed in
         if ina:
             hi, hi_seen = probe, True
         else:
             lo, lo_seen = probe, True
         if by_surrogate:
             if rho[-1] > 0:
-                shift = probe - match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
+                j = match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
+                if levels is not None:
+                    # the level places the run where it discriminates (it
+                    # changes by LEVEL_STEP or more per cell there); where it
+                    # is flat (deep in the active phase) the curve shape does
+                    jl = level_index(levels, delta_eff_windows(times, rho)[1], probe, lo0, hi0)
+                    a, b = max(jl - 1, 0), min(jl + 1, len(levels) - 1)
+                    if np.isfinite(levels[a]) and np.isfinite(levels[b]) and \
+                            abs(levels[b] - levels[a]) >= 2 * LEVEL_STEP:
+                        j = jl
+                shift = probe - j
             else:
                 placed = calibrated  # extinct: no calibration, midpoints from here on
     return lo, hi
@@ -302,20 +350,67 @@ def plain_bisect(d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
     return res["plain"]
 
 
-def predicted_class(times, log10_rho) -> bool:
+def predicted_class(times, log10_rho, flip_level: float = DELTA_HIGH) -> bool:
     """Class of a surrogate curve for placing probes: inactive when its
-    delta_eff over the last half-decade exceeds DELTA_HIGH. The network
+    delta_eff over the last half-decade exceeds `flip_level`. The network
     reproduces the level of delta_eff near p_c (about 0.2 at p_c, 1/2 for
     decaying runs) better than the change of delta_eff between half-decades,
     on which classify() also relies; simulated runs are classified by
-    classify()."""
+    classify(). `flip_level` is the level at which classify() turns to
+    inactive on the training curves of this d (flip_levels), DELTA_HIGH
+    without one."""
     r = 10.0 ** np.asarray(log10_rho, float)
-    return bool(delta_eff_windows(times, r)[1] > DELTA_HIGH)
+    return bool(delta_eff_windows(times, r)[1] > flip_level)
 
 
-def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
+def flip_levels(p, d, t, y, m, times):
+    """For each d of a training set, the delta_eff level (last half-decade)
+    that best separates its curves into the classes classify() gives them:
+    the threshold with the fewest curves on the wrong side. Rows are
+    (p, d, t, log10 rho, mask); a curve is the rows of one (p, d). Returns
+    {d: level}."""
+    p, d, t, y, m = (np.asarray(a, float) for a in (p, d, t, y, m))
+    out = {}
+    for dv in np.unique(d):
+        sel = d == dv
+        pc, inv = np.unique(p[sel], return_inverse=True)
+        levels, classes = [], []
+        for c in range(len(pc)):
+            rows = np.nonzero(inv == c)[0]
+            order = np.argsort(t[sel][rows])
+            tt = t[sel][rows][order]
+            rho = np.where(m[sel][rows][order] > 0, 10.0 ** y[sel][rows][order], 0.0)
+            if len(tt) != len(times):
+                continue
+            ina = classify(tt, rho)
+            lvl = delta_eff_windows(tt, rho)[1] if rho[-1] > 0 else np.inf
+            levels.append(lvl)
+            classes.append(ina)
+        levels, classes = np.asarray(levels), np.asarray(classes, bool)
+        finite = np.sort(np.unique(levels[np.isfinite(levels)]))
+        if finite.size < 2:
+            out[float(dv)] = DELTA_HIGH
+            continue
+        cands = 0.5 * (finite[1:] + finite[:-1])
+        errors = np.array([int(np.sum((levels > c) != classes)) for c in cands])
+        # the middle of the run of candidates with the fewest errors
+        best = np.nonzero(errors == errors.min())[0]
+        out[float(dv)] = float(0.5 * (cands[best[0]] + cands[best[-1]]))
+    return out
+
+
+def level_for(flip: Optional[dict], d: float) -> float:
+    """flip_levels value for d (linear in d between the training d values)."""
+    if not flip:
+        return DELTA_HIGH
+    ds = np.array(sorted(flip), float)
+    return float(np.interp(d, ds, [flip[k] for k in sorted(flip)]))
+
+
+def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec,
+                      flip: Optional[dict] = None):
     """Surrogate curves log10 rho(p_j, d, t_k) and their classes
-    (predicted_class) for grid indices idx."""
+    (predicted_class at the flip level for d) for grid indices idx."""
     import torch
 
     times = np.asarray(spec.times(), float)
@@ -323,20 +418,22 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec):
     T = np.tile(times, len(idx))
     x = torch.from_numpy(features(P, d, T)).cuda()
     y = net.predict(x).cpu().numpy().astype(np.float64).reshape(len(idx), len(times))
-    cls = [predicted_class(times, y[k]) for k in range(len(idx))]
+    lvl = level_for(flip, d)
+    cls = [predicted_class(times, y[k], lvl) for k in range(len(idx))]
     return y, np.array(cls, dtype=bool)
 
 
 def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
                      lo: int = 0, hi: Optional[int] = None, predictor=None,
-                     calibrated: int = CALIBRATED_PROBES, domain=None):
+                     calibrated: int = CALIBRATED_PROBES, domain=None,
+                     calibration: str = "level"):
     """The surrogate-guided search alone; `predictor(d, idx)` -> (log10 rho
     [len(idx), times], classes) replaces the network (tests). `domain` is the
     network's training p range (see restrict_to_domain)."""
     hi = len(grid) - 1 if hi is None else hi
     predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
     ys, cls = restrict_to_domain(*predictor(d, list(range(len(grid)))), grid, domain)
-    gen = surrogate_steps(ys, cls, grid, spec.times(), lo, hi, calibrated)
+    gen = surrogate_steps(ys, cls, grid, spec.times(), lo, hi, calibrated, calibration)
     res = drive({"surrogate": (gen, d, d_idx)}, spec, grid, _sequential(runner))
     return res["surrogate"]
 
@@ -413,11 +510,13 @@ def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-
 def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
                     train_count: int = 512, train_batches: int = 2, train_L=(1 << 14, 1 << 16),
                     epochs: int = 150, seed: int = 2013, log=print, p_range=(0.04, 0.30),
-                    data_path: Optional[str] = None):
+                    data_path: Optional[str] = None, max_data_s: float = float("inf")):
     """Simulate the training curves (batched runs at the search's horizon) and
     train a surrogate on them. Returns (net, training summary). With
     `data_path`, the simulated set (features, targets, mask, site updates) is
-    read from that .npz file if it exists, else written there."""
+    read from that .npz file if it exists, else written there, each batch
+    also to a file of its own; batches not yet cached are simulated only
+    while less than `max_data_s` seconds have passed (TimeoutError after)."""
     import os
     import time
 
@@ -427,49 +526,67 @@ def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
     t0 = time.perf_counter()
     if data_path and os.path.exists(data_path):
         with np.load(data_path) as z:
-            x = features(z["p"], z["d"], z["t"])
+            P, D, T = z["p"], z["d"], z["t"]
             y, m, train_su = z["y"], z["m"], int(z["site_updates"])
         log(f"training set read from {data_path}: {len(y)} rows")
     else:
         raws, ys, ms, train_su = [], [], [], 0
         for b in range(train_batches):
-            insts = training_batch(train_count, spec, seed + b, d_values=d_values,
-                                   L_range=train_L, p_range=p_range)
-            _, y, m, su = simulate_training_set(insts, spec, seed + b)
-            raws.append(training_rows(insts, spec.times())), ys.append(y), ms.append(m)
+            # each batch is cached on its own, so a long set can be simulated
+            # over several processes
+            bpath = f"{os.path.splitext(data_path)[0]}.b{b}.npz" if data_path else None
+            if bpath and os.path.exists(bpath):
+                with np.load(bpath) as z:
+                    raw, y, m, su = (z["p"], z["d"], z["t"]), z["y"], z["m"], int(z["site_updates"])
+            else:
+                if time.perf_counter() - t0 > max_data_s:
+                    raise TimeoutError(f"training batch {b}: time budget spent; cached batches "
+                                       f"are kept, run again to continue")
+                insts = training_batch(train_count, spec, seed + b, d_values=d_values,
+                                       L_range=train_L, p_range=p_range)
+                _, y, m, su = simulate_training_set(insts, spec, seed + b)
+                raw = training_rows(insts, spec.times())
+                if bpath:
+                    np.savez(bpath, p=raw[0], d=raw[1], t=raw[2], y=y, m=m,
+                             site_updates=np.int64(su))
+            raws.append(raw), ys.append(y), ms.append(m)
             train_su += su
-            log(f"training batch {b + 1}/{train_batches}: {len(insts)} curves, "
+            log(f"training batch {b + 1}/{train_batches}: {len(y) // len(spec.times())} curves, "
                 f"{time.perf_counter() - t0:.1f} s")
         P, D, T = (np.concatenate([r[k] for r in raws]) for k in range(3))
         y, m = np.concatenate(ys), np.concatenate(ms)
-        x = features(P, D, T)
         if data_path:
             np.savez(data_path, p=P, d=D, t=T, y=y, m=m, site_updates=np.int64(train_su))
+    x = features(P, D, T)
     t_data = time.perf_counter() - t0
+    flip = flip_levels(P, D, T, y, m, spec.times())
+    log(f"flip levels from the training curves: {flip}")
     net = pcpd.Surrogate(seed=seed)
     t1 = time.perf_counter()
     loss = train(net, x, y, m, epochs=epochs, seed=seed, log=log)
     t_train = time.perf_counter() - t1
     return net, {"curves": int(len(y) // len(spec.times())), "rows": int(len(y)),
                  "site_updates": train_su, "data_s": t_data, "train_s": t_train,
-                 "final_loss": loss}
+                 "final_loss": loss, "flip_levels": flip}
 
 
 def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print, runner=None,
-                 predictor=None, domain=None):
+                 predictor=None, domain=None, calibration: str = "level",
+                 flip: Optional[dict] = None):
     """Plain and surrogate-guided searches for every d, all driven in
     lockstep (one batched GPU run per round), each with its own ledger and
     cache: no run is shared between searches. `domain` is the network's
     training p range. Returns one record per d."""
     import time
 
-    predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec))
+    predictor = predictor or (lambda dd, idx: predicted_classes(net, dd, idx, grid, spec, flip))
     hi = len(grid) - 1
     searches = {}
     for d, k in zip(d_values, d_indices):
         ys, cls = restrict_to_domain(*predictor(d, list(range(len(grid)))), grid, domain)
         searches[("plain", k)] = (plain_steps(grid, 0, hi), d, k)
-        searches[("surrogate", k)] = (surrogate_steps(ys, cls, grid, spec.times(), 0, hi), d, k)
+        searches[("surrogate", k)] = (surrogate_steps(ys, cls, grid, spec.times(), 0, hi,
+                                                      calibration=calibration), d, k)
     t0 = time.perf_counter()
     res = drive(searches, spec, grid, runner, log)
     wall = time.perf_counter() - t0
@@ -515,6 +632,7 @@ def compare(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None, bits: int 
 def main(argv=None):
     import argparse
     import json
+    import os
 
     ap = argparse.ArgumentParser(description="p_c search, plain vs surrogate-guided")
     ap.add_argument("--L", type=int, default=1 << 18)
@@ -538,6 +656,14 @@ def main(argv=None):
                     help="training set cache (.npz): read if present, else simulated and written")
     ap.add_argument("--train-d", type=str, default=None,
                     help="d values of the training curves (default: the searched --d)")
+    ap.add_argument("--calibration", choices=("level", "shape"), default="level",
+                    help="how a simulated probe is placed on the network's p axis")
+    ap.add_argument("--seed", type=int, default=2013, help="training set and network seed")
+    ap.add_argument("--max-data-s", type=float, default=float("inf"),
+                    help="stop simulating training batches after this many seconds "
+                         "(cached batches are kept; run again to continue)")
+    ap.add_argument("--no-flip-levels", action="store_true",
+                    help="place probes with the fixed level DELTA_HIGH, not the learned ones")
     a = ap.parse_args(argv)
     from . import pcpd
 
@@ -548,22 +674,37 @@ def main(argv=None):
     res = {"spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps, "grid": len(grid),
                     "p_range": [float(grid.p[0]), float(grid.p[-1])]},
            "training": None, "searches": []}
+    flip = None
     if a.load_net:
         net = pcpd.Surrogate(seed=0)
         net.set_params(np.load(a.load_net))
+        meta = os.path.splitext(a.load_net)[0] + ".json"
+        if os.path.exists(meta):
+            with open(meta) as f:
+                flip = {float(k): float(v) for k, v in json.load(f)["flip_levels"].items()}
     else:
         train_d = d_values if a.train_d is None else tuple(float(v) for v in a.train_d.split(","))
         net, res["training"] = build_surrogate(
             train_d, spec, a.train_count, a.train_batches,
-            tuple(int(v) for v in a.train_L.split(",")), a.epochs, log=log,
-            p_range=tuple(float(v) for v in a.train_p.split(",")), data_path=a.train_data)
+            tuple(int(v) for v in a.train_L.split(",")), a.epochs, seed=a.seed, log=log,
+            p_range=tuple(float(v) for v in a.train_p.split(",")), data_path=a.train_data,
+            max_data_s=a.max_data_s)
         print(json.dumps({"training": res["training"]}), flush=True)
+        flip = res["training"]["flip_levels"]
     if a.save_net:
         np.save(a.save_net, net.params())
+        with open(os.path.splitext(a.save_net)[0] + ".json", "w") as f:
+            json.dump({"flip_levels": {str(k): v for k, v in (flip or {}).items()},
+                       "train_p": [float(v) for v in a.train_p.split(",")],
+                       "train_d": a.train_d or a.d, "train_L": a.train_L,
+                       "spec": {"L": spec.L, "planes": spec.planes, "steps": spec.steps,
+                                "bits": a.bits}}, f, indent=1)
     if not a.train_only:
         keep = range(len(d_values)) if a.d_index is None else [int(v) for v in a.d_index.split(",")]
         res["searches"] = run_searches(net, [d_values[k] for k in keep], list(keep), spec, grid,
-                                       log, domain=tuple(float(v) for v in a.train_p.split(",")))
+                                       log, domain=tuple(float(v) for v in a.train_p.split(",")),
+                                       calibration=a.calibration,
+                                       flip=None if a.no_flip_levels else flip)
     net.close()
     print(json.dumps(res), flush=True)
 
