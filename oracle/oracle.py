@@ -52,6 +52,7 @@ class _Params(ctypes.Structure):
         ("words_out", ctypes.POINTER(ctypes.c_uint64)),
         ("n_out", ctypes.POINTER(ctypes.c_uint64)),
         ("pair_out", ctypes.POINTER(ctypes.c_uint64)),
+        ("connected", ctypes.c_int32),
     ]
 
 
@@ -84,6 +85,9 @@ def lib():
         L.orc_simulate_many.restype = ctypes.c_int
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = ctypes.c_int32
+        L.orc_connected_substep.argtypes = [ctypes.c_int, u32, u64, u32, u32, u32, u64, u64, u64,
+                                            ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_connected_substep.restype = None
         _lib = L
     return _lib
 
@@ -120,7 +124,8 @@ class Run:
     """One (instance, plane) unit: inputs plus the output arrays it fills."""
 
     def __init__(self, *, model="pcpd", B=64, L, seed=1, stream=0, plane=0, p, d,
-                 samples=(1 << 64) - 1, init="full", init_words=None, t0=0, times):
+                 samples=(1 << 64) - 1, init="full", init_words=None, t0=0, times,
+                 connected=False):
         self.times = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
         self.words = np.zeros(int(L), dtype=np.uint64)
         self.n = np.zeros((len(self.times), 64), dtype=np.uint64)
@@ -148,6 +153,7 @@ class Run:
         P.words_out = _ptr(self.words)
         P.n_out = _ptr(self.n)
         P.pair_out = _ptr(self.pair)
+        P.connected = 1 if connected else 0
         self.params = P
 
     # aggregated observables over the simulated samples, per record
@@ -159,6 +165,18 @@ class Run:
         for b in range(64):
             alive |= (self.n[:, b] > 0).astype(np.uint64) << np.uint64(b)
         return N, NP, alive
+
+
+def connected_substep(model, B, L, seed, stream, plane, p, d, s, sites):
+    """One substep s on a joined ring of 64 L sites given as a uint8 array
+    (global site order); returns the new array."""
+    q = np.ascontiguousarray(np.asarray(sites, dtype=np.uint8)).copy()
+    assert q.shape == (64 * int(L),)
+    n = MODEL_N[model] if isinstance(model, str) else int(model)
+    lib().orc_connected_substep(n, int(B), int(L), int(seed), int(stream), int(plane),
+                                threshold(d), threshold(p), int(s),
+                                q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return q
 
 
 def simulate(run: Run) -> Run:

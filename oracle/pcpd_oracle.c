@@ -231,7 +231,10 @@ typedef struct {
     uint64_t *words_out;   /* L words: final lattice (bits of unsimulated samples are 0) */
     uint64_t *n_out;       /* [n_times][64] particles per sample */
     uint64_t *pair_out;    /* [n_times][64] pairs per sample */
+    int32_t connected;     /* 1: the 64 bits form one joined lattice (orc_simulate_connected) */
 } orc_params;
+
+static int orc_simulate_connected(const orc_params *P);
 
 /* Error codes: 0 ok, -1 invalid arguments, -2 out of memory. */
 int orc_simulate(const orc_params *P)
@@ -256,6 +259,8 @@ int orc_simulate(const orc_params *P)
         if (P->times[r] < P->t0 || (r > 0 && P->times[r] <= P->times[r - 1]))
             return -1;
 
+    if (P->connected)
+        return orc_simulate_connected(P);
     nblocks = P->L / P->B;
     for (b = 0; b < 64; b++) {
         lat[b] = NULL;
@@ -332,6 +337,102 @@ done:
     for (b = 0; b < 64; b++)
         free(lat[b]);
     return rc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Connected multispin lattice (paper Sec. 4, second paragraph, and the layout
+ * of its Figs. 2-3): instead of 64 independent rings, the 64 bits of a plane
+ * are joined into ONE ring of M = 64 L sites. Site g = b*L + j is bit b of
+ * word j, so the sites held by one word are L apart (the paper's L/N_r for a
+ * lattice of M sites and N_r = 64 bits). Neighbours follow the global site
+ * order: after word L-1 of bit b comes word 0 of bit b+1, and after bit 63
+ * comes bit 0 (the ring closes). A window that runs past the last word of the
+ * plane therefore continues in the next bit of the first words -- the bit
+ * rotation at the seam that connects the lattices.
+ *
+ * Site selection is the Sec. 3 scheme on the joined ring: M is cut into M/B
+ * blocks, global block K = b*(L/B) + k (k = the word block, b = the bit), and
+ * substep s attempts every block at its local site o (the same draw as in the
+ * classical layout), i.e. at global site g = K*B + o = b*L + k*B + o. The
+ * decision bits of that window are bit b of the masks of word window k
+ * (the same Philox counters as the classical layout): each global window
+ * reads its own bit, as each sample does in the classical layout.
+ * Observables per bit column b (sites b*L .. b*L+L-1): particles, and pairs
+ * (g, g+1) with g in the column (the pair leaving the column's last site
+ * pairs it with the first site of column b+1).
+ * ------------------------------------------------------------------------- */
+
+/* One substep s of the Sec. 3 scheme on a joined ring of M = 64 L sites held
+ * as bytes (q[g] for global site g). */
+void orc_connected_substep(int n, uint32_t B, uint64_t L, uint32_t seed, uint32_t stream,
+                           uint32_t plane, uint64_t Kd, uint64_t Kp, uint64_t s, uint8_t *q)
+{
+    uint64_t nblocks = L / B, M = 64u * L, k;
+    uint32_t o = orc_offset(seed, stream, plane, s, B);
+    int b;
+    for (k = 0; k < nblocks; k++) {
+        orc_draws w = window_draws(seed, stream, plane, s, (uint32_t)k);
+        for (b = 0; b < 64; b++) {
+            uint64_t g = (uint64_t)b * L + k * B + o; /* global block b*nblocks + k */
+            int D = orc_decide(w.x1d, w.x2d, w.gd, Kd, b);
+            int A = orc_decide(w.x1a, w.x2a, w.ga, Kp, b);
+            int R = (int)((w.r >> b) & 1u);
+            attempt(n, q, M, g, D, A, R);
+        }
+    }
+}
+
+static int orc_simulate_connected(const orc_params *P)
+{
+    uint64_t M = 64u * P->L, Kd, Kp, t, j, g;
+    uint8_t *q;
+    uint32_t r, sub;
+    int b;
+    Kd = orc_threshold(P->d);
+    Kp = orc_threshold(P->p);
+    if (Kd == UINT64_MAX || Kp == UINT64_MAX)
+        return -1;
+    q = (uint8_t *)malloc(M);
+    if (!q)
+        return -2;
+    for (b = 0; b < 64; b++)
+        for (j = 0; j < P->L; j++) {
+            g = (uint64_t)b * P->L + j;
+            if (P->init == 0)
+                q[g] = 1;
+            else if (P->init == 1)
+                q[g] = 0;
+            else
+                q[g] = (uint8_t)((P->init_words[j] >> b) & 1u);
+        }
+    t = P->t0;
+    for (r = 0; r < P->n_times; r++) {
+        for (; t < P->times[r]; t++)
+            for (sub = 0; sub < P->B; sub++)
+                orc_connected_substep(P->n, P->B, P->L, P->seed, P->stream, P->plane, Kd, Kp,
+                                      t * (uint64_t)P->B + sub, q);
+        for (b = 0; b < 64; b++) {
+            uint64_t cnt = 0, pairs = 0;
+            for (j = 0; j < P->L; j++) {
+                g = (uint64_t)b * P->L + j;
+                cnt += q[g];
+                pairs += (uint64_t)(q[g] & q[(g + 1) % M]);
+            }
+            if (P->n_out)
+                P->n_out[(uint64_t)r * 64 + b] = cnt;
+            if (P->pair_out)
+                P->pair_out[(uint64_t)r * 64 + b] = pairs;
+        }
+    }
+    if (P->words_out)
+        for (j = 0; j < P->L; j++) {
+            uint64_t w = 0;
+            for (b = 0; b < 64; b++)
+                w |= (uint64_t)q[(uint64_t)b * P->L + j] << b;
+            P->words_out[j] = w;
+        }
+    free(q);
+    return 0;
 }
 
 /* Independent (instance, plane) units in parallel, one per thread; there is
