@@ -61,6 +61,10 @@ def parse():
                     help="time the library's tile shapes on the workload first (untimed)")
     ap.add_argument("--teams", type=int, default=0, choices=(0, 2, 4),
                     help="lanes per block of the phase kernel (0 = the library's default)")
+    ap.add_argument("--tile-cols", type=int, default=0,
+                    help="tile width in blocks, halo included (0 = the library's default)")
+    ap.add_argument("--phase-max", type=int, default=0,
+                    help="most substeps per phase launch (0 = the library's default)")
     ap.add_argument("--persistent", action="store_true",
                     help="all phases between records in one ticket-dispatched launch")
     return ap.parse_args()
@@ -144,8 +148,8 @@ def main():
         del src, dst
 
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
-    if args.teams:
-        sim.set_tuning(0, 0, args.teams)
+    if args.teams or args.tile_cols or args.phase_max:
+        sim.set_tuning(args.tile_cols, args.phase_max, args.teams)
     if args.persistent:
         sim.set_options(persistent=True)
     if args.autotune:

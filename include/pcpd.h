@@ -73,12 +73,26 @@ typedef enum { PCPD_DP = 1, PCPD_PCPD = 2, PCPD_TCPD = 3, PCPD_QCPD = 4 } pcpd_m
 
 typedef enum { PCPD_INIT_FULL = 0, PCPD_INIT_EMPTY = 1, PCPD_INIT_HOST = 2 } pcpd_init_kind;
 
+/* Multispin layout of a plane (paper Sec. 4). */
+typedef enum {
+    PCPD_LAYOUT_CLASSICAL = 0, /* 64 independent rings of L sites, one per bit */
+    PCPD_LAYOUT_CONNECTED = 1  /* the 64 bits joined into ONE ring of 64 L sites: site
+                                  b*L + j is bit b of word j (the sites of a word are L apart),
+                                  and past word L-1 of bit b comes word 0 of bit b+1 (Sec. 4,
+                                  second paragraph; the layout of Figs. 2-3). The Sec. 3 scheme
+                                  runs on the joined ring (64 L / B blocks); the window at site
+                                  b*L + k*B + o reads bit b of word window k's draws. N_pair
+                                  counts the pairs of the joined ring; alive has bit b set iff
+                                  sites b*L .. b*L+L-1 hold a particle. */
+} pcpd_layout;
+
 /* Shared by all instances of a context. */
 typedef struct {
     int32_t model;    /* pcpd_model */
     uint32_t B;       /* block width; B >= n+2; every L must be a multiple of B */
-    uint32_t planes;  /* planes per instance, >= 1; 64 samples each */
+    uint32_t planes;  /* planes per instance, >= 1; 64 samples (or one joined ring) each */
     uint32_t seed;    /* Philox key word 0 */
+    uint32_t layout;  /* pcpd_layout */
 } pcpd_config;
 
 /* One independent simulation (its own rates, ring length and Philox stream). */

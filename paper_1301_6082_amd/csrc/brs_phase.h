@@ -113,10 +113,34 @@ __device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb
     }
 }
 
-template <int KDH, int KPH>
-__device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uint64_t s) {
+// Draw identity of a lane's window: its block k. In the connected layout a
+// tile with columns past the ends of the word ring runs with LapWin, which
+// also carries the lap of the lane's column (a right rotation by rot = lap mod
+// 64; zero for columns inside the ring); every other tile runs with PlainWin,
+// whose code has no trace of the rotation.
+struct PlainWin {
+    static constexpr bool kLapped = false;
+    uint32_t k;
+    uint32_t rot;  // unused
+};
+struct LapWin {
+    static constexpr bool kLapped = true;
+    uint32_t k;
+    uint32_t rot;
+};
+
+// Right rotation of a 64-bit mask held as two halves, by r in 0..63.
+__device__ __forceinline__ W2 rotr_w2(W2 x, uint32_t r) {
+    const bool sw = (r & 32u) != 0u;
+    const uint32_t lo = sw ? x.hi : x.lo, hi = sw ? x.lo : x.hi;
+    return W2{__builtin_amdgcn_alignbit(hi, lo, r & 31u), __builtin_amdgcn_alignbit(lo, hi, r & 31u)};
+}
+
+template <int KDH, int KPH, typename Win>
+__device__ __forceinline__ Masks window_masks(const LatDesc &ld, Win w, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
+    const uint32_t k = w.k;
     U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
     philox10_x3(x, ld.key0, ld.key1);
     const U4 &d = x[0], &a = x[1], &r = x[2];
@@ -130,6 +154,13 @@ __device__ __forceinline__ Masks window_masks(const LatDesc &ld, uint32_t k, uin
     m.Am.hi = Decide<KPH>::half(a.y, a.w, ta);
     m.R.lo = r.x;
     m.R.hi = r.y;
+    if constexpr (Win::kLapped) {
+        // bit b of a lapped column holds the site of bit b + lap of its block:
+        // its decisions are that bit's, moved like the column's words
+        m.D = rotr_w2(m.D, w.rot);
+        m.Am = rotr_w2(m.Am, w.rot);
+        m.R = rotr_w2(m.R, w.rot);
+    }
     return m;
 }
 
@@ -257,8 +288,8 @@ __device__ __forceinline__ bool windows_disjoint(uint32_t oa, uint32_t ob, uint3
 // address. Lanes whose window would leave the loaded columns (block 0 when
 // o == 0, the last block when o+N >= B, lanes past the tile) work on the
 // spare columns trash-1 .. trash+1 instead, so no branch depends on the lane.
-template <int N, int KDH, int KPH>
-__device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+template <int N, int KDH, int KPH, typename Win>
+__device__ __forceinline__ void run_substeps(uint64_t *lds, const LatDesc &ld, Win kg,
                                              uint32_t c, uint32_t team, uint32_t ncols,
                                              uint32_t trash, uint64_t s0, uint32_t S, uint32_t B,
                                              uint32_t ldw) {
@@ -370,8 +401,8 @@ __device__ __forceinline__ uint32_t group_run_index(uint32_t sites, uint32_t B) 
 // of the run at once. A team draws the masks of its next substep (T later)
 // between the loads and the arithmetic of its update. Every wavefront passes
 // the same barriers: each computes the same cut from the same local sites.
-template <int N, int KDH, int KPH, int T>
-__device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+template <int N, int KDH, int KPH, int T, typename Win>
+__device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc &ld, Win kg,
                                                    uint32_t c, uint32_t team, uint32_t ncols,
                                                    uint32_t trash, uint64_t s0, uint32_t S,
                                                    uint32_t B, uint32_t ldw) {
@@ -420,8 +451,8 @@ __device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc 
 }
 
 // T = 2 runs the two-team loop above; T = 4 the general one.
-template <int N, int KDH, int KPH, int T>
-__device__ __forceinline__ void run_team_loop(uint64_t *lds, const LatDesc &ld, uint32_t kg,
+template <int N, int KDH, int KPH, int T, typename Win>
+__device__ __forceinline__ void run_team_loop(uint64_t *lds, const LatDesc &ld, Win kg,
                                               uint32_t c, uint32_t team, uint32_t ncols,
                                               uint32_t trash, uint64_t s0, uint32_t S, uint32_t B,
                                               uint32_t ldw) {
@@ -431,9 +462,9 @@ __device__ __forceinline__ void run_team_loop(uint64_t *lds, const LatDesc &ld, 
         run_substeps_teams<N, KDH, KPH, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw);
 }
 
-template <int N, int KDH, int T>
+template <int N, int KDH, int T, typename Win>
 __device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
-                                            uint32_t kg, uint32_t c, uint32_t team, uint32_t ncols,
+                                            Win kg, uint32_t c, uint32_t team, uint32_t ncols,
                                             uint32_t trash,
                                             uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
     switch (ld.kp_hi) {
@@ -443,6 +474,35 @@ __device__ __forceinline__ void dispatch_kp(uint64_t *lds, const LatDesc &ld,
         case 3: run_team_loop<N, KDH, 3, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
         default: run_team_loop<N, KDH, 4, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
     }
+}
+
+template <int N, int T, typename Win>
+__device__ __forceinline__ void dispatch_kd(uint64_t *lds, const LatDesc &ld, Win kg, uint32_t c,
+                                            uint32_t team, uint32_t ncols, uint32_t trash,
+                                            uint64_t s0, uint32_t S, uint32_t B, uint32_t ldw) {
+    switch (ld.kd_hi) {
+        case 0: dispatch_kp<N, 0, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 1: dispatch_kp<N, 1, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 2: dispatch_kp<N, 2, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        case 3: dispatch_kp<N, 3, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        default: dispatch_kp<N, 4, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+    }
+}
+
+// Connected layout (the 64 bits of a plane joined into one ring of 64 L
+// sites, bit b of word j = site b*L + j): the tile's column of virtual block
+// v (v < 0 or v >= nb past the ends of the word ring) holds the words of
+// block v mod nb moved by m = floor(v / nb) laps, i.e. with every site m*L
+// further on, which is bit b+m of the stored word: a right rotation by m.
+__device__ __forceinline__ int32_t ring_lap(int64_t v, uint32_t nb) {
+    if (v >= 0 && v < static_cast<int64_t>(nb)) return 0;
+    if (v >= 0) return static_cast<int32_t>(v / nb);
+    return -static_cast<int32_t>((-v + nb - 1) / nb);
+}
+
+__device__ __forceinline__ uint64_t rotr64(uint64_t x, int32_t m) {
+    const uint32_t r = static_cast<uint32_t>(m) & 63u;
+    return r ? (x >> r) | (x << (64u - r)) : x;
 }
 
 // Words moved per lane per batch between HBM and LDS: independent loads in
@@ -625,6 +685,27 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
         load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
     __syncthreads();
 
+    // ---- connected layout: rotate the columns loaded from past the ends of
+    // the word ring (only at a ring's first and last tiles, or in rings
+    // shorter than the tile): front columns [0, lo_end), back [hi_start, ncols)
+    if (ld.connected) {
+        const int64_t v0 = static_cast<int64_t>(td.k0) - hb;  // virtual block of column 0
+        const uint32_t lo_end =
+            v0 < 0 ? static_cast<uint32_t>(-v0 < static_cast<int64_t>(ncols) ? -v0 : ncols) : 0u;
+        const int64_t hs = static_cast<int64_t>(nb) - v0;
+        const uint32_t hi_start = hs <= 0 ? 0u : (hs >= ncols ? ncols : static_cast<uint32_t>(hs));
+        const uint32_t nout = lo_end >= hi_start ? ncols : lo_end + (ncols - hi_start);
+        if (nout > 0u) {
+            for (uint32_t i = tid; i < nout * B; i += nthr) {
+                const uint32_t idx = i / B, o = i - idx * B;
+                const uint32_t c = lo_end >= hi_start ? idx : (idx < lo_end ? idx : hi_start + idx - lo_end);
+                const int32_t m = ring_lap(v0 + c, nb);
+                if (m != 0) lds[o * ldw + c] = rotr64(lds[o * ldw + c], m);
+            }
+            __syncthreads();
+        }
+    }
+
     // ---- S substeps in LDS, one window (block) per lane
     {
         // per is a multiple of the wavefront size, so the team is uniform
@@ -633,14 +714,14 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
         const uint32_t team = __builtin_amdgcn_readfirstlane(tid / per);
         const uint32_t c = tid - team * per;
         const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
-        uint32_t kg = kfirst + c;
-        if (kg >= nb) kg %= nb;
-        switch (ld.kd_hi) {
-            case 0: dispatch_kp<N, 0, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 1: dispatch_kp<N, 1, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 2: dispatch_kp<N, 2, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            case 3: dispatch_kp<N, 3, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
-            default: dispatch_kp<N, 4, T>(lds, ld, kg, c, team, ncols, trash, s0, S, B, ldw); break;
+        uint32_t kb = kfirst + c;
+        if (kb >= nb) kb %= nb;
+        const int64_t v0 = static_cast<int64_t>(td.k0) - hb;
+        if (ld.connected && (v0 < 0 || v0 + static_cast<int64_t>(ncols) > static_cast<int64_t>(nb))) {
+            const uint32_t rot = c < ncols ? static_cast<uint32_t>(ring_lap(v0 + c, nb)) & 63u : 0u;
+            dispatch_kd<N, T>(lds, ld, LapWin{kb, rot}, c, team, ncols, trash, s0, S, B, ldw);
+        } else {
+            dispatch_kd<N, T>(lds, ld, PlainWin{kb, 0u}, c, team, ncols, trash, s0, S, B, ldw);
         }
     }
 

@@ -112,6 +112,8 @@ int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
              bool check_init = true) {
     if (!cfg || !inst || n_inst == 0) return PCPD_EINVAL;
     if (cfg->model < 1 || cfg->model > 4) return PCPD_EINVAL;
+    if (cfg->layout != PCPD_LAYOUT_CLASSICAL && cfg->layout != PCPD_LAYOUT_CONNECTED)
+        return PCPD_EINVAL;
     const uint32_t n = static_cast<uint32_t>(cfg->model);
     if (cfg->B < n + 2 || cfg->planes == 0 || cfg->planes >= (1u << 29)) return PCPD_EINVAL;
     uint64_t total = 0;
@@ -279,6 +281,7 @@ std::vector<LatDesc> plan_lats(const pcpd_config *cfg, const pcpd_instance *inst
             ld.kd_lo = static_cast<uint32_t>(kd);
             ld.kp_hi = static_cast<uint32_t>(kp >> 32);
             ld.kp_lo = static_cast<uint32_t>(kp);
+            ld.connected = cfg->layout == PCPD_LAYOUT_CONNECTED ? 1u : 0u;
             lats.push_back(ld);
         }
         base += inst[i].L * cfg->planes;

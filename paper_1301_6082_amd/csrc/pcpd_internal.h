@@ -10,7 +10,7 @@
 namespace pcpd {
 
 // One (instance, plane): a ring of nblocks*B words at word offset `base` of
-// each lattice copy. 48 bytes, read once per workgroup into SGPRs.
+// each lattice copy. 56 bytes, read once per workgroup into SGPRs.
 struct LatDesc {
     uint64_t base;     // word offset of site 0
     uint64_t L;        // sites (words) in the ring
@@ -22,6 +22,8 @@ struct LatDesc {
     uint32_t kd_lo;
     uint32_t kp_hi;    // annihilation threshold K_p
     uint32_t kp_lo;
+    uint32_t connected;  // 1: the 64 bits form one joined ring of 64 L sites
+    uint32_t pad;
 };
 
 // One workgroup's tile: interior blocks [k0, k0 + kint) of lattice `lat`.

@@ -30,7 +30,10 @@ density_chunks(const uint64_t *__restrict__ buf, const LatDesc *__restrict__ lat
         const uint64_t j = ch.w0 + i;
         const uint64_t jn = (j + 1 == ld.L) ? 0 : j + 1;
         const uint64_t w = ring[j];
-        const uint64_t wn = ring[jn];
+        uint64_t wn = ring[jn];
+        // connected layout: after the last word of bit b comes the first word
+        // of bit b+1 (site b*L + L-1 pairs with (b+1)*L)
+        if (ld.connected && jn == 0) wn = (wn >> 1) | (wn << 63);
         n += __popcll(w);
         np += __popcll(w & wn);
         alive |= w;

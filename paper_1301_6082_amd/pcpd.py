@@ -28,8 +28,11 @@ INIT_FULL, INIT_EMPTY, INIT_HOST = 0, 1, 2
 u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
 
 
+LAYOUT_CLASSICAL, LAYOUT_CONNECTED = 0, 1
+
+
 class Config(ctypes.Structure):
-    _fields_ = [("model", i32), ("B", u32), ("planes", u32), ("seed", u32)]
+    _fields_ = [("model", i32), ("B", u32), ("planes", u32), ("seed", u32), ("layout", u32)]
 
 
 class InstanceC(ctypes.Structure):
@@ -144,8 +147,8 @@ def _instances(insts, planes):
     return arr, keep
 
 
-def lattice_bytes(model: int, B: int, planes: int, seed: int, instances) -> int:
-    cfg = Config(int(model), int(B), int(planes), int(seed))
+def lattice_bytes(model: int, B: int, planes: int, seed: int, instances, layout: int = 0) -> int:
+    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout))
     arr, _ = _instances(instances, planes)
     out = ctypes.c_size_t()
     _check(_lib.pcpd_lattice_bytes(ctypes.byref(cfg), arr, len(instances), ctypes.byref(out)),
@@ -158,15 +161,16 @@ class Sim:
     p, d, L, stream_id, init, host_words) sharing model, B, planes and seed."""
 
     def __init__(self, model: int, B: int, planes: int, seed: int, instances, t0: int = 0,
-                 device: int | None = None, torch_buffer: bool = True):
+                 device: int | None = None, torch_buffer: bool = True, layout: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("libpcpd needs a ROCm GPU; none is visible")
         self.model, self.B, self.planes, self.seed = int(model), int(B), int(planes), int(seed)
+        self.layout = int(layout)
         self.instances = list(instances)
         self.n_inst = len(self.instances)
         self.Ls = [int(i.L) for i in self.instances]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        cfg = Config(self.model, self.B, self.planes, self.seed)
+        cfg = Config(self.model, self.B, self.planes, self.seed, self.layout)
         arr, keep = _instances(self.instances, self.planes)
         dev = Device()
         with torch.cuda.device(self.device):
@@ -174,7 +178,8 @@ class Sim:
             dev.hip_stream = ctypes.c_void_p(self.stream.cuda_stream)
             self._buf = None
             if torch_buffer:
-                nbytes = lattice_bytes(self.model, self.B, self.planes, self.seed, self.instances)
+                nbytes = lattice_bytes(self.model, self.B, self.planes, self.seed, self.instances,
+                                       self.layout)
                 self._buf = torch.empty(nbytes // 8, dtype=torch.int64, device=self.device)
                 dev.dev_buf = ctypes.c_void_p(self._buf.data_ptr())
                 dev.dev_buf_bytes = nbytes
@@ -274,7 +279,7 @@ class Sim:
 
 
 def run_noalloc(model: int, B: int, planes: int, seed: int, instances, t0: int,
-                lattice: torch.Tensor, times: Sequence[int]) -> np.ndarray:
+                lattice: torch.Tensor, times: Sequence[int], layout: int = 0) -> np.ndarray:
     """pcpd_run_noalloc: advance the lattice held in `lattice` (a contiguous
     int64 CUDA tensor of planes * sum L words, instance-major then
     plane-major) from step t0 through `times`, in place, without any device
@@ -284,7 +289,7 @@ def run_noalloc(model: int, B: int, planes: int, seed: int, instances, t0: int,
     if not (isinstance(lattice, torch.Tensor) and lattice.is_cuda and lattice.dtype == torch.int64
             and lattice.is_contiguous() and lattice.numel() == words):
         raise ValueError(f"lattice must be a contiguous int64 CUDA tensor of {words} words")
-    cfg = Config(int(model), int(B), int(planes), int(seed))
+    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout))
     arr, keep = _instances(instances, planes)
     t = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
     out = (CountsC * (len(t) * len(instances) * planes))()

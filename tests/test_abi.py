@@ -47,8 +47,8 @@ def test_strerror(mod):
     assert lib.pcpd_strerror(42) == b"unknown status"
 
 
-def _cfg(mod, model=2, B=64, planes=1, seed=1):
-    return mod.Config(model, B, planes, seed)
+def _cfg(mod, model=2, B=64, planes=1, seed=1, layout=0):
+    return mod.Config(model, B, planes, seed, layout)
 
 
 def _inst(mod, p=0.1, d=0.5, L=1024, init=0, words=None):
@@ -64,7 +64,7 @@ BAD = [
     dict(inst=dict(p=-0.1)), dict(inst=dict(p=1.5)), dict(inst=dict(d=float("nan"))),
     dict(inst=dict(d=float("inf"))), dict(inst=dict(L=100)), dict(inst=dict(L=32)),
     dict(inst=dict(L=0)), dict(inst=dict(init=3)), dict(inst=dict(init=2, words=None)),
-    dict(inst=dict(L=64 << 32)),
+    dict(inst=dict(L=64 << 32)), dict(cfg=dict(layout=2)),
 ]
 
 

@@ -23,19 +23,20 @@ def pcpd():
 
 
 def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t0=0,
-                  options=None):
+                  options=None, layout=0):
     """GPU run with records at `times` vs the oracle on every plane, all samples."""
     print(f"[parity] model={model} B={B} planes={planes} n_inst={len(instances)} "
           f"L={[i.L for i in instances]} times={times[:4]}..{times[-1]} tuning={tuning} "
-          f"options={options}", flush=True)
-    with pcpd.Sim(model, B, planes, seed, instances, t0=t0) as sim:
+          f"options={options} layout={layout}", flush=True)
+    with pcpd.Sim(model, B, planes, seed, instances, t0=t0, layout=layout) as sim:
         if tuning:
             sim.set_tuning(*tuning)
         if options:
             sim.set_options(**options)
         counts = sim.run(times)
         lat = [sim.get_lattice(i) for i in range(len(instances))]
-    keys, runs = oracle_runs(model, B, planes, seed, instances, times, t0=t0)
+    keys, runs = oracle_runs(model, B, planes, seed, instances, times, t0=t0,
+                             connected=layout == 1)
     for (i, q), r in zip(keys, runs):
         L = instances[i].L
         np.testing.assert_array_equal(lat[i][q * L:(q + 1) * L], r.words,
@@ -362,3 +363,32 @@ def test_persistent_cfg3_batch_matches_direct(pcpd):
         np.testing.assert_array_equal(cp, cd)
         for i in (0, 77, 300, 511):
             np.testing.assert_array_equal(p.get_lattice(i), d.get_lattice(i), err_msg=f"inst {i}")
+
+
+# ---- connected multispin layout ----------------------------------------------
+
+@pytest.mark.parametrize("teams", [2, 4])
+@pytest.mark.parametrize("shape", [(128, 128), (64, 16), (40, 7), (9, 1)])
+def test_connected_layout_matches_oracle(pcpd, shape, teams):
+    """The 64 bits of each plane joined into one ring (paper Sec. 4): rings of
+    many tiles, of one tile, and of fewer blocks than the halo (columns many
+    laps around the word ring, each rotated by its lap count)."""
+    insts = [Instance(0.12, 0.4, 64 * 301, 3), Instance(0.2, 0.1, 64 * 7, 4),
+             Instance(0.05, 0.8, 64 * 1200, 5), Instance(0.3, 0.5, 64, 6)]
+    _compare_full(pcpd, 2, 64, 2, 11, insts, [0, 1, 4, 9], tuning=(*shape, teams), layout=1)
+
+
+@pytest.mark.parametrize("L,B,model", [(64 * 260, 64, 1), (64 * 260, 64, 3), (64 * 40, 64, 4),
+                                       (15 * 1400, 15, 2), (1000, 8, 2), (6, 6, 4), (12, 4, 2)])
+def test_connected_layout_models_and_block_widths(pcpd, L, B, model):
+    start = wl.random_lattice(L, 2, 0.5, 77)
+    insts = [Instance(0.15, 0.4, L, 5, wl.INIT_HOST, start), Instance(0.1, 0.7, L, 6)]
+    _compare_full(pcpd, model, B, 2, 4, insts, [3, 10], layout=1)
+
+
+def test_connected_layout_persistent_and_graph(pcpd):
+    insts = [Instance(0.1, 0.3, 64 * 200, 0), Instance(0.22, 0.6, 64 * 37, 1)]
+    _compare_full(pcpd, 2, 64, 2, 4, insts, [2, 5, 11], tuning=(64, 16, 2),
+                  options={"persistent": True}, layout=1)
+    _compare_full(pcpd, 2, 64, 2, 4, insts, [2, 40], tuning=(128, 4, 2),
+                  options={"graph": True}, layout=1)
