@@ -188,6 +188,58 @@ def level_index(levels, level_sim: float, probe: int, lo: int = 0, hi: Optional[
     return int(near[np.argmin(np.abs(near - probe))])
 
 
+def rising_segment(levels, f0: int, tol: float = 0.01) -> Tuple[int, int]:
+    """The stretch [a, b] around the surrogate's flip f0 over which its
+    predicted delta_eff level rises with p: extended down while the level
+    does not go up by more than `tol` per cell, and up while it does not go
+    down by more than `tol` (small wiggles of the network pass)."""
+    levels = np.asarray(levels, float)
+    n = len(levels)
+    f0 = min(max(int(f0), 0), n - 1)
+    a = b = f0
+    while a > 0 and np.isfinite(levels[a - 1]) and levels[a - 1] <= levels[a] + tol:
+        a -= 1
+    while b + 1 < n and np.isfinite(levels[b + 1]) and levels[b + 1] >= levels[b] - tol:
+        b += 1
+    return a, b
+
+
+def crossing_index(levels, level_sim: float, f0: int, tol: float = 0.01) -> float:
+    """Where the predicted level equals a simulated run's level, on the
+    rising stretch around f0 and nearest f0: from f0 down to the first cell
+    at or below the simulated level when that lies below the level at f0,
+    else up to the first cell at or above it (linear between cells). A level
+    below the whole lower stretch goes to the foot of the rise, the last cell
+    below f0 within `tol` of the stretch's floor; one above the upper stretch
+    goes to its top. Near p_c the level of a run rises by a tenth or more per
+    cell, so a run placed this way tells how far the surrogate's flip is off;
+    the same level far from the flip, where the predicted curves are flat or
+    saturated, does not."""
+    levels = np.asarray(levels, float)
+    a, b = rising_segment(levels, f0, tol)
+    f = min(max(int(f0), a), b)
+    if not np.isfinite(levels[f]):
+        return float(f)
+    if level_sim <= levels[f]:
+        i = f
+        while i > a and levels[i] > level_sim:
+            i -= 1
+        if levels[i] > level_sim:
+            floor = float(np.min(levels[a:f + 1]))
+            return float(a + int(np.nonzero(levels[a:f + 1] <= floor + tol)[0][-1]))
+        if i == f:
+            return float(f)
+        lo, hi = levels[i], levels[i + 1]
+        return i + (float((level_sim - lo) / (hi - lo)) if hi > lo else 0.0)
+    i = f
+    while i < b and levels[i] < level_sim:
+        i += 1
+    if levels[i] < level_sim:
+        return float(b)
+    lo, hi = levels[i - 1], levels[i]
+    return i - 1 + (float((level_sim - lo) / (hi - lo)) if hi > lo else 1.0)
+
+
 def predicted_levels(ys, times):
     """delta_eff over the last half-decade of each predicted log10 rho curve."""
     ys = np.asarray(ys, float)
@@ -213,15 +265,18 @@ def restrict_to_domain(ys, cls, grid: Grid, domain=None):
 
 
 def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
-                    calibrated: int = CALIBRATED_PROBES, calibration: str = "level"):
+                    calibrated: int = CALIBRATED_PROBES, calibration: str = "crossing"):
     """Bracket search whose probes the surrogate places. `ys` [grid, times]
     are its log10 rho curves for the whole grid and `cls` their classes; its
     flip f0 is where its last run of inactive predictions inside the bracket
     starts.
     Each simulated probe calibrates it: the grid index j where the surrogate
-    puts the simulated curve, so that its flip moves by (probe - j). j is the
+    puts the simulated curve, so that its flip moves by (probe - j). With
+    calibration="crossing" (the default) j is where the predicted delta_eff
+    level of the last half-decade, on its rising stretch around the flip,
+    equals the simulated run's (crossing_index). Otherwise j is the
     index whose predicted curve is closest over the last decade of t
-    (match_index); with calibration="level" (the default), where the
+    (match_index, calibration="shape"); with calibration="level", where the
     predicted delta_eff level of the last half-decade changes by LEVEL_STEP
     or more per cell, j is instead the index with the closest level
     (level_index): near and above the flip the level rises steeply with p
@@ -237,19 +292,19 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
     ys = np.asarray(ys, float)
     cls = np.asarray(cls, bool)
     late = np.asarray(times, float) >= float(times[-1]) / 10.0
-    levels = predicted_levels(ys, times) if calibration == "level" else None
+    levels = predicted_levels(ys, times) if calibration in ("level", "crossing") else None
     # the surrogate's flip: the start of its last run of inactive predictions
     # inside the bracket (spurious inactive predictions far below it, e.g.
     # where the network extrapolates, do not count)
     active_pred = np.nonzero(~cls[lo + 1:hi + 1])[0]
     f0 = lo + 2 + int(active_pred[-1]) if active_pred.size else lo + 1
     f0 = min(f0, hi)
-    shift, placed, streak, last_end = 0, 0, 0, None
+    shift, placed, streak, last_end = 0.0, 0, 0, None
     lo_seen = hi_seen = False  # ends of the bracket established by simulation
     while hi - lo > 1:
         by_surrogate = placed < calibrated
         if by_surrogate:
-            f = f0 + shift
+            f = int(round(f0 + shift))
             end = "hi" if f >= hi else ("lo" if f <= lo + 1 else None)
             streak = streak + 1 if (end is not None and end == last_end) else 0
             last_end = end
@@ -278,7 +333,9 @@ def surrogate_steps(ys, cls, grid: Grid, times, lo: int, hi: int,
         else:
             lo, lo_seen = probe, True
         if by_surrogate:
-            if rho[-1] > 0:
+            if rho[-1] > 0 and calibration == "crossing":
+                shift = probe - crossing_index(levels, delta_eff_windows(times, rho)[1], f0)
+            elif rho[-1] > 0:
                 j = match_index(ys, np.log10(np.maximum(rho, 1e-300)), late)
                 if levels is not None:
                     # the level places the run where it discriminates (it
@@ -426,7 +483,7 @@ def predicted_classes(net, d, idx: Sequence[int], grid: Grid, spec: RunSpec,
 def surrogate_bisect(net, d, d_idx, grid: Grid, spec: RunSpec, runner=simulate_curve,
                      lo: int = 0, hi: Optional[int] = None, predictor=None,
                      calibrated: int = CALIBRATED_PROBES, domain=None,
-                     calibration: str = "level"):
+                     calibration: str = "crossing"):
     """The surrogate-guided search alone; `predictor(d, idx)` -> (log10 rho
     [len(idx), times], classes) replaces the network (tests). `domain` is the
     network's training p range (see restrict_to_domain)."""
@@ -499,8 +556,8 @@ def train(net, x, y, mask, epochs: int = 200, batch: int = 8192, lr: float = 2e-
             idx = perm[s:s + batch]
             net.train_step(X[idx].contiguous(), Y[idx].contiguous(), M[idx].contiguous(), lr=step_lr)
         if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
-            log(f"epoch {ep}: loss {net.grads(X, Y, M)[0]:.5f}")
-    return net.grads(X, Y, M)[0]
+            log(f"epoch {ep}: loss {net.loss(X, Y, M):.5f}")
+    return net.loss(X, Y, M)
 
 
 # --------------------------------------------------------------------------
@@ -571,7 +628,7 @@ def build_surrogate(d_values=(0.1, 0.5, 0.9), spec: Optional[RunSpec] = None,
 
 
 def run_searches(net, d_values, d_indices, spec: RunSpec, grid: Grid, log=print, runner=None,
-                 predictor=None, domain=None, calibration: str = "level",
+                 predictor=None, domain=None, calibration: str = "crossing",
                  flip: Optional[dict] = None):
     """Plain and surrogate-guided searches for every d, all driven in
     lockstep (one batched GPU run per round), each with its own ledger and
@@ -656,7 +713,7 @@ def main(argv=None):
                     help="training set cache (.npz): read if present, else simulated and written")
     ap.add_argument("--train-d", type=str, default=None,
                     help="d values of the training curves (default: the searched --d)")
-    ap.add_argument("--calibration", choices=("level", "shape"), default="level",
+    ap.add_argument("--calibration", choices=("crossing", "level", "shape"), default="crossing",
                     help="how a simulated probe is placed on the network's p axis")
     ap.add_argument("--seed", type=int, default=2013, help="training set and network seed")
     ap.add_argument("--max-data-s", type=float, default=float("inf"),

@@ -313,3 +313,47 @@ def test_two_sided_proposals_stay_in_the_middle_half():
                                             predictor=garbage)
         assert (lo, hi) == (F - 1, F)
         assert led.runs <= ps.CALIBRATED_PROBES + 10
+
+
+def _levels_with_rise(n=300, foot=150, rise=10, top=0.8, floor=0.0):
+    lv = np.full(n, floor)
+    lv[foot:foot + rise + 1] = np.linspace(floor, top, rise + 1)
+    lv[foot + rise + 1:] = top
+    return lv
+
+
+def test_crossing_index_reads_the_rise_around_the_flip():
+    lv = _levels_with_rise()              # rises 0.08 per cell over 150..160
+    assert ps.rising_segment(lv, 155) == (0, 299)
+    assert ps.crossing_index(lv, 0.40, 155) == pytest.approx(155.0)
+    assert ps.crossing_index(lv, 0.44, 155) == pytest.approx(155.5)
+    assert ps.crossing_index(lv, 0.0, 155) == 150.0     # active run: the foot of the rise
+    assert ps.crossing_index(lv, -0.3, 155) == 150.0
+    assert ps.crossing_index(lv, 2.0, 155) == 299.0      # beyond the top: the top
+
+
+def test_crossing_index_ignores_matching_levels_away_from_the_flip():
+    """A network level far below the flip that happens to equal the simulated
+    one (a wiggle in its flat active phase) must not place the run there: the
+    rising stretch around the flip ends at the wiggle."""
+    lv = _levels_with_rise()
+    lv[40] = 0.03                          # the wiggle
+    lv += 0.004 * np.sin(np.arange(lv.size))   # small noise on the flat parts
+    a, b = ps.rising_segment(lv, 155)
+    assert 40 < a <= 150 and b == 299
+    j = ps.crossing_index(lv, 0.03, 155)
+    assert 150 <= j <= 151
+    assert ps.level_index(lv, 0.03, 155) == 40   # what matching the whole grid would pick
+
+
+@pytest.mark.parametrize("F,bias", [(333, 3), (485, -3), (780, -7), (120, 12)])
+def test_crossing_calibration_recovers_a_shifted_flip(F, bias):
+    """Runs whose last-half-decade level rises through the flip (the family
+    above) and a surrogate shifted by `bias`: the first run calibrates it,
+    and the search closes in at most three runs, on the plain bracket."""
+    grid = ps.Grid(bits=10)
+    (lo, hi), led = ps.surrogate_bisect(None, 0.5, 1, grid, SPEC, runner=_family_runner(F),
+                                        predictor=_family_predictor(F + bias),
+                                        calibration="crossing")
+    assert (lo, hi) == (F - 1, F)
+    assert led.runs <= 3
