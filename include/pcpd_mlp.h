@@ -38,7 +38,12 @@ extern "C" {
 #endif
 
 #define PCPD_MLP_PARAMS 33665
+/* Rows of one predict / loss call, and of one gradient / training call. A
+ * gradient call keeps the pre-activations of every row on the device
+ * (1.5 KiB per row: 1.6 GB at the limit) plus at most 512 gradient partials
+ * (69 MB) whatever N; predict and loss keep 8 bytes per 64 rows. */
 #define PCPD_MLP_MAX_ROWS (1u << 24)
+#define PCPD_MLP_MAX_TRAIN_ROWS (1u << 20)
 
 typedef struct pcpd_mlp pcpd_mlp;
 
@@ -55,13 +60,21 @@ PCPD_API int pcpd_mlp_set_params(pcpd_mlp *net, const float *host_params);
 /* y_dev[r] = network(x_dev[r]) for r < N (N <= PCPD_MLP_MAX_ROWS). Asynchronous. */
 PCPD_API int pcpd_mlp_predict(pcpd_mlp *net, const float *x_dev, uint32_t N, float *y_dev);
 
+/* Masked mean squared error of the network on N rows (N <= PCPD_MLP_MAX_ROWS),
+ * forward pass only; the outputs go to y_dev[N]. mask_dev may be NULL (all
+ * rows). Synchronises. */
+PCPD_API int pcpd_mlp_loss(pcpd_mlp *net, const float *x_dev, const float *target_dev,
+                           const float *mask_dev, uint32_t N, float *y_dev, float *loss_out);
+
 /* Loss and gradient (host, PCPD_MLP_PARAMS floats) of the masked mean squared
- * error at the current parameters; mask_dev may be NULL (all rows). Synchronises. */
+ * error at the current parameters (N <= PCPD_MLP_MAX_TRAIN_ROWS); mask_dev may
+ * be NULL (all rows). Synchronises. */
 PCPD_API int pcpd_mlp_grads(pcpd_mlp *net, const float *x_dev, const float *target_dev,
                             const float *mask_dev, uint32_t N, float *host_grads,
                             float *loss_out);
 
-/* One Adam step on the masked mean squared error of this batch. If loss_out is
+/* One Adam step on the masked mean squared error of this batch
+ * (N <= PCPD_MLP_MAX_TRAIN_ROWS). If loss_out is
  * not NULL the loss before the step is returned (this synchronises). */
 PCPD_API int pcpd_mlp_train_step(pcpd_mlp *net, const float *x_dev, const float *target_dev,
                                  const float *mask_dev, uint32_t N, float lr, float *loss_out);

@@ -97,14 +97,15 @@ __device__ __forceinline__ void hidden_layer(const bfbits *hin, const bfbits *__
         for (int j = 0; j < 4; ++j) {
             const int r = 16 * wave + 4 * (lane >> 4) + j, u = 16 * nt + (lane & 15);
             const float z = acc[nt][j] + bias[u];
-            if (r0 + r < N) zout[static_cast<size_t>(r0 + r) * H + u] = z;
+            if (zout && r0 + r < N) zout[static_cast<size_t>(r0 + r) * H + u] = z;
             hout[r * LDH + u] = f2bf(gelu(z));
         }
     }
 }
 
 // Forward pass of one 64-row tile; with a target, also the tile's masked
-// squared error and mask count (part[2*wg], part[2*wg+1]).
+// squared error and mask count (part[2*wg], part[2*wg+1]). The pre-activations
+// z1..z3 are kept for the backward pass only when z1 is not null.
 __global__ void __launch_bounds__(THREADS)
 mlp_forward(const float *__restrict__ x, uint32_t N, const float *__restrict__ theta,
             const bfbits *__restrict__ W2b, const bfbits *__restrict__ W3b,
@@ -127,7 +128,7 @@ mlp_forward(const float *__restrict__ x, uint32_t N, const float *__restrict__ t
             for (int k = 0; k < 3; ++k)
                 acc = fmaf(rbf(x[static_cast<size_t>(gr) * 3 + k]), rbf(theta[oW1 + u * 3 + k]), acc);
             z = acc + theta[ob1 + u];
-            z1[static_cast<size_t>(gr) * H + u] = z;
+            if (z1) z1[static_cast<size_t>(gr) * H + u] = z;
         }
         hA[r * LDH + u] = f2bf(gelu(z));
     }
@@ -207,7 +208,7 @@ mlp_loss_finalize(const float *__restrict__ loss_part, uint32_t nwg, float *__re
 // tile, from the transposed tiles dzT [H][ROWS] and hT [H][ROWS] in LDS.
 // Wavefront w computes i in 32w..32w+31 (two row blocks), all j.
 __device__ __forceinline__ void weight_grad(const bfbits *dzT, const bfbits *hT,
-                                            float *__restrict__ out) {
+                                            float *__restrict__ out, bool accumulate) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -226,8 +227,10 @@ __device__ __forceinline__ void weight_grad(const bfbits *dzT, const bfbits *hT,
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                out[(16 * mt + 4 * (lane >> 4) + j) * H + 16 * nt + (lane & 15)] = acc[nt][j];
+            for (int j = 0; j < 4; ++j) {
+                float *o = out + (16 * mt + 4 * (lane >> 4) + j) * H + 16 * nt + (lane & 15);
+                *o = accumulate ? *o + acc[nt][j] : acc[nt][j];
+            }
     }
 }
 
@@ -249,8 +252,11 @@ __device__ __forceinline__ void input_grad(const bfbits *dz, const bfbits *__res
     }
 }
 
-// Backward pass of one 64-row tile: all gradients of this tile into
-// part[wg * NP .. + NP) (summed over tiles by mlp_reduce).
+// Backward pass of the 64-row tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// in that order: their gradients summed into part[wg * NP .. + NP) (then
+// summed over workgroups by mlp_reduce). The grid is capped, so the partials
+// take at most kBwdGrid * NP floats whatever the number of rows. Every
+// partial element is read and written by one fixed thread, in program order.
 __global__ void __launch_bounds__(THREADS)
 mlp_backward(const float *__restrict__ x, const float *__restrict__ target,
              const float *__restrict__ mask, uint32_t N, const float *__restrict__ theta,
@@ -265,9 +271,14 @@ mlp_backward(const float *__restrict__ x, const float *__restrict__ target,
     __shared__ float dy[ROWS];
     __shared__ float colsum[2][H];
     const int tid = threadIdx.x;
-    const uint32_t r0 = blockIdx.x * ROWS;
     float *out = part + static_cast<size_t>(blockIdx.x) * NP;
     const float M = scal[1];
+    const uint32_t ntiles = (N + ROWS - 1) / ROWS;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint32_t r0 = tile * ROWS;
+    const bool acc_on = tile != blockIdx.x;  // add to the partial of earlier tiles
+    auto put = [&](uint32_t i, float v) { out[i] = acc_on ? out[i] + v : v; };
+    __syncthreads();  // the previous tile is done with the shared buffers
 
     if (tid < ROWS) {
         const uint32_t gr = r0 + tid;
@@ -307,17 +318,17 @@ mlp_backward(const float *__restrict__ x, const float *__restrict__ target,
         }
         __syncthreads();
         if (rh == 0) {
-            out[ow4 + j] = sw4 + colsum[0][j];
-            out[ob3 + j] = sb3 + colsum[1][j];
+            put(ow4 + j, sw4 + colsum[0][j]);
+            put(ob3 + j, sb3 + colsum[1][j]);
         }
         if (tid == 0) {
             float s = 0.f;
             for (int r = 0; r < ROWS; ++r) s += dy[r];
-            out[ob4] = s;
+            put(ob4, s);
         }
     }
     __syncthreads();
-    weight_grad(dzT, hT, out + oW3);
+    weight_grad(dzT, hT, out + oW3, acc_on);
 
     // layer 2: dh2 = bf(dz3) W3, dz2 = dh2 gelu'(z2)
     {
@@ -348,9 +359,9 @@ mlp_backward(const float *__restrict__ x, const float *__restrict__ target,
     if (tid < H) {
         float s = 0.f;
         for (int r = 0; r < ROWS; ++r) s += zf[r * H + tid];
-        out[ob2 + tid] = s;
+        put(ob2 + tid, s);
     }
-    weight_grad(dzT, hT, out + oW2);
+    weight_grad(dzT, hT, out + oW2, acc_on);
 
     // layer 1: dh1 = bf(dz2) W2, dz1 = dh1 gelu'(z1), 3-input weights on vector lanes
     {
@@ -379,9 +390,10 @@ mlp_backward(const float *__restrict__ x, const float *__restrict__ target,
             s = fmaf(zf[r * H + i], xv, s);
         }
         if (k < 3)
-            out[oW1 + i * 3 + k] = s;
+            put(oW1 + i * 3 + k, s);
         else
-            out[ob1 + i] = s;
+            put(ob1 + i, s);
+    }
     }
 }
 
@@ -445,8 +457,8 @@ struct pcpd_mlp {
     float *scal = nullptr;  // loss, M
     float *z = nullptr;     // z1, z2, z3 for cap_rows rows
     float *ytmp = nullptr;  // cap_rows
-    float *loss_part = nullptr;
-    float *part = nullptr;  // cap_wg * NP
+    float *loss_part = nullptr;  // 2 * cap_wg
+    float *part = nullptr;  // bwd_grid(cap_rows) * NP
     uint32_t cap_rows = 0, cap_wg = 0;
     float *h_scal = nullptr;  // pinned
     int64_t step = 0;
@@ -472,37 +484,62 @@ hipError_t prep(pcpd_mlp *n) {
     return hipGetLastError();
 }
 
-// Scratch sized for N rows (grown on demand; the stream is synchronised first).
-hipError_t reserve(pcpd_mlp *n, uint32_t N) {
+// Workgroups of the backward pass at most: each sums the gradients of its
+// tiles into one partial (NP floats), so the partials take at most
+// kBwdGrid * NP * 4 bytes (69 MB) for any number of rows; 512 workgroups
+// cover the 256 CUs twice.
+constexpr uint32_t kBwdGrid = 512;
+
+uint32_t bwd_grid(uint32_t N) {
     const uint32_t nwg = (N + pcpd::ROWS - 1) / pcpd::ROWS;
-    if (N <= n->cap_rows && nwg <= n->cap_wg) return hipSuccess;
-    hipError_t e = hipStreamSynchronize(n->stream);
-    if (e != hipSuccess) return e;
-    (void)hipFree(n->z);
-    (void)hipFree(n->ytmp);
-    (void)hipFree(n->loss_part);
-    (void)hipFree(n->part);
-    n->z = n->ytmp = n->loss_part = n->part = nullptr;
-    n->cap_rows = n->cap_wg = 0;
+    return nwg < kBwdGrid ? nwg : kBwdGrid;
+}
+
+// Scratch for N rows, grown on demand (the stream is synchronised first):
+// the loss partials (2 floats per 64-row tile) always; for a gradient
+// (train = true, N <= PCPD_MLP_MAX_TRAIN_ROWS) also the pre-activations of
+// every row (3 * 128 floats), the outputs and the backward partials.
+hipError_t reserve(pcpd_mlp *n, uint32_t N, bool train) {
+    const uint32_t nwg = (N + pcpd::ROWS - 1) / pcpd::ROWS;
     const size_t rows = static_cast<size_t>(nwg) * pcpd::ROWS;
-    if ((e = hipMalloc(&n->z, 3 * rows * pcpd::H * sizeof(float))) != hipSuccess) return e;
-    if ((e = hipMalloc(&n->ytmp, rows * sizeof(float))) != hipSuccess) return e;
-    if ((e = hipMalloc(&n->loss_part, 2 * static_cast<size_t>(nwg) * sizeof(float))) != hipSuccess)
-        return e;
-    if ((e = hipMalloc(&n->part, static_cast<size_t>(nwg) * pcpd::NP * sizeof(float))) != hipSuccess)
-        return e;
-    n->cap_rows = static_cast<uint32_t>(rows);
-    n->cap_wg = nwg;
+    hipError_t e = hipSuccess;
+    if (nwg > n->cap_wg) {
+        if ((e = hipStreamSynchronize(n->stream)) != hipSuccess) return e;
+        (void)hipFree(n->loss_part);
+        n->loss_part = nullptr;
+        n->cap_wg = 0;
+        if ((e = hipMalloc(&n->loss_part, 2 * static_cast<size_t>(nwg) * sizeof(float))) != hipSuccess)
+            return e;
+        n->cap_wg = nwg;
+    }
+    if (train && rows > n->cap_rows) {
+        if ((e = hipStreamSynchronize(n->stream)) != hipSuccess) return e;
+        (void)hipFree(n->z);
+        (void)hipFree(n->ytmp);
+        (void)hipFree(n->part);
+        n->z = n->ytmp = n->part = nullptr;
+        n->cap_rows = 0;
+        if ((e = hipMalloc(&n->z, 3 * rows * pcpd::H * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc(&n->ytmp, rows * sizeof(float))) != hipSuccess) return e;
+        if ((e = hipMalloc(&n->part, static_cast<size_t>(bwd_grid(N)) * pcpd::NP * sizeof(float))) !=
+            hipSuccess)
+            return e;
+        n->cap_rows = static_cast<uint32_t>(rows);
+    }
     return hipSuccess;
 }
 
+// keep_z: store the pre-activations for a backward pass (scratch reserved
+// with train = true).
 hipError_t forward(pcpd_mlp *n, const float *x, uint32_t N, float *y, const float *target,
-                   const float *mask) {
+                   const float *mask, bool keep_z) {
     const uint32_t nwg = (N + pcpd::ROWS - 1) / pcpd::ROWS;
     const size_t rows = static_cast<size_t>(n->cap_rows);
+    float *z1 = keep_z ? n->z : nullptr;
+    float *z2 = keep_z ? n->z + rows * pcpd::H : nullptr;
+    float *z3 = keep_z ? n->z + 2 * rows * pcpd::H : nullptr;
     hipLaunchKernelGGL(pcpd::mlp_forward, dim3(nwg), dim3(pcpd::THREADS), 0, n->stream, x, N,
-                       n->theta, W2b(n), W3b(n), n->z, n->z + rows * pcpd::H,
-                       n->z + 2 * rows * pcpd::H, y, target, mask, n->loss_part);
+                       n->theta, W2b(n), W3b(n), z1, z2, z3, y, target, mask, n->loss_part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !target) return e;
     hipLaunchKernelGGL(pcpd::mlp_loss_finalize, dim3(1), dim3(pcpd::THREADS), 0, n->stream,
@@ -512,7 +549,7 @@ hipError_t forward(pcpd_mlp *n, const float *x, uint32_t N, float *y, const floa
 
 hipError_t backward(pcpd_mlp *n, const float *x, const float *target, const float *mask,
                     uint32_t N) {
-    const uint32_t nwg = (N + pcpd::ROWS - 1) / pcpd::ROWS;
+    const uint32_t nwg = bwd_grid(N);
     const size_t rows = static_cast<size_t>(n->cap_rows);
     hipLaunchKernelGGL(pcpd::mlp_backward, dim3(nwg), dim3(pcpd::THREADS), 0, n->stream, x,
                        target, mask, N, n->theta, W2bT(n), W3bT(n), n->z, n->z + rows * pcpd::H,
@@ -525,6 +562,7 @@ hipError_t backward(pcpd_mlp *n, const float *x, const float *target, const floa
 }
 
 bool rows_ok(uint32_t N) { return N >= 1 && N <= PCPD_MLP_MAX_ROWS; }
+bool train_rows_ok(uint32_t N) { return N >= 1 && N <= PCPD_MLP_MAX_TRAIN_ROWS; }
 
 }  // namespace
 
@@ -583,17 +621,31 @@ int pcpd_mlp_set_params(pcpd_mlp *n, const float *host_params) {
 int pcpd_mlp_predict(pcpd_mlp *n, const float *x_dev, uint32_t N, float *y_dev) {
     if (!n || !x_dev || !y_dev || !rows_ok(N)) return PCPD_EINVAL;
     if (n->broken) return PCPD_ESTATE;
-    hipError_t e = reserve(n, N);
-    if (e == hipSuccess) e = forward(n, x_dev, N, y_dev, nullptr, nullptr);
+    hipError_t e = reserve(n, N, false);
+    if (e == hipSuccess) e = forward(n, x_dev, N, y_dev, nullptr, nullptr, false);
     return mfail(n, e);
+}
+
+int pcpd_mlp_loss(pcpd_mlp *n, const float *x_dev, const float *target_dev,
+                  const float *mask_dev, uint32_t N, float *y_dev, float *loss_out) {
+    if (!n || !x_dev || !target_dev || !y_dev || !loss_out || !rows_ok(N)) return PCPD_EINVAL;
+    if (n->broken) return PCPD_ESTATE;
+    hipError_t e = reserve(n, N, false);
+    if (e == hipSuccess) e = forward(n, x_dev, N, y_dev, target_dev, mask_dev, false);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(n->h_scal, n->scal, 2 * sizeof(float), hipMemcpyDeviceToHost, n->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    if (e != hipSuccess) return mfail(n, e);
+    *loss_out = n->h_scal[0];
+    return PCPD_OK;
 }
 
 int pcpd_mlp_grads(pcpd_mlp *n, const float *x_dev, const float *target_dev,
                    const float *mask_dev, uint32_t N, float *host_grads, float *loss_out) {
-    if (!n || !x_dev || !target_dev || !host_grads || !rows_ok(N)) return PCPD_EINVAL;
+    if (!n || !x_dev || !target_dev || !host_grads || !train_rows_ok(N)) return PCPD_EINVAL;
     if (n->broken) return PCPD_ESTATE;
-    hipError_t e = reserve(n, N);
-    if (e == hipSuccess) e = forward(n, x_dev, N, n->ytmp, target_dev, mask_dev);
+    hipError_t e = reserve(n, N, true);
+    if (e == hipSuccess) e = forward(n, x_dev, N, n->ytmp, target_dev, mask_dev, true);
     if (e == hipSuccess) e = backward(n, x_dev, target_dev, mask_dev, N);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_grads, n->grad, pcpd::NP * sizeof(float), hipMemcpyDeviceToHost,
@@ -608,10 +660,10 @@ int pcpd_mlp_grads(pcpd_mlp *n, const float *x_dev, const float *target_dev,
 
 int pcpd_mlp_train_step(pcpd_mlp *n, const float *x_dev, const float *target_dev,
                         const float *mask_dev, uint32_t N, float lr, float *loss_out) {
-    if (!n || !x_dev || !target_dev || !rows_ok(N) || !(lr >= 0.f)) return PCPD_EINVAL;
+    if (!n || !x_dev || !target_dev || !train_rows_ok(N) || !(lr >= 0.f)) return PCPD_EINVAL;
     if (n->broken) return PCPD_ESTATE;
-    hipError_t e = reserve(n, N);
-    if (e == hipSuccess) e = forward(n, x_dev, N, n->ytmp, target_dev, mask_dev);
+    hipError_t e = reserve(n, N, true);
+    if (e == hipSuccess) e = forward(n, x_dev, N, n->ytmp, target_dev, mask_dev, true);
     if (e == hipSuccess) e = backward(n, x_dev, target_dev, mask_dev, N);
     if (e == hipSuccess && loss_out)
         e = hipMemcpyAsync(n->h_scal, n->scal, 2 * sizeof(float), hipMemcpyDeviceToHost, n->stream);

@@ -59,8 +59,10 @@ EXPORTS = ["pcpd_lattice_bytes", "pcpd_init", "pcpd_sweep", "pcpd_density", "pcp
            "pcpd_profile", "pcpd_profile_read", "pcpd_run_noalloc",
            "pcpd_device_error", "pcpd_free", "pcpd_strerror"]
 MLP_EXPORTS = ["pcpd_mlp_init", "pcpd_mlp_get_params", "pcpd_mlp_set_params", "pcpd_mlp_predict",
-               "pcpd_mlp_grads", "pcpd_mlp_train_step", "pcpd_mlp_free"]
+               "pcpd_mlp_loss", "pcpd_mlp_grads", "pcpd_mlp_train_step", "pcpd_mlp_free"]
 MLP_PARAMS = 33665
+MLP_MAX_ROWS = 1 << 24
+MLP_MAX_TRAIN_ROWS = 1 << 20
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "pcpd_mlp_get_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_set_params": ([vp, P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_predict": ([vp, vp, u32, vp], ctypes.c_int),
+        "pcpd_mlp_loss": ([vp, vp, vp, vp, u32, vp, P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_grads": ([vp, vp, vp, vp, u32, P(ctypes.c_float), P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_train_step": ([vp, vp, vp, vp, u32, ctypes.c_float, P(ctypes.c_float)], ctypes.c_int),
         "pcpd_mlp_free": ([vp], ctypes.c_int),
@@ -341,6 +344,18 @@ class Surrogate:
         _check(_lib.pcpd_mlp_predict(self._net, _dev_f32(x, (n, 3), "x"), n,
                                      ctypes.c_void_p(y.data_ptr())), "pcpd_mlp_predict")
         return y
+
+    def loss(self, x, target, mask=None) -> float:
+        """Masked mean squared error, forward pass only (no gradient scratch)."""
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        m = _dev_f32(mask, (n,), "mask") if mask is not None else None
+        _check(_lib.pcpd_mlp_loss(self._net, _dev_f32(x, (n, 3), "x"),
+                                  _dev_f32(target, (n,), "target"), m, n,
+                                  ctypes.c_void_p(y.data_ptr()), ctypes.byref(loss)),
+               "pcpd_mlp_loss")
+        return float(loss.value)
 
     def grads(self, x, target, mask=None):
         n = x.shape[0]

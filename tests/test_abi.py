@@ -132,3 +132,20 @@ def test_noalloc_run_checks_its_limits_before_any_device_work(mod):
     assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, fake, late, 1, out, None) == -5
     # no records: nothing to do, the lattice is left as it is
     assert lib.pcpd_run_noalloc(ctypes.byref(one), ok, 1, 0, fake, None, 0, None, None) == 0
+
+
+def test_mlp_limits_match_the_header(mod):
+    import os
+    import re
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "pcpd_mlp.h")).read()
+    macros = {k: eval(v.replace("u", "")) for k, v in
+              re.findall(r"#define (PCPD_MLP_\w+) \(?([0-9u <]+)\)?", text)}
+    assert macros["PCPD_MLP_PARAMS"] == mod.MLP_PARAMS
+    assert macros["PCPD_MLP_MAX_ROWS"] == mod.MLP_MAX_ROWS
+    assert macros["PCPD_MLP_MAX_TRAIN_ROWS"] == mod.MLP_MAX_TRAIN_ROWS
+
+
+def test_mlp_calls_refuse_bad_arguments_without_a_device(mod):
+    lib = mod._lib
+    f = ctypes.c_float()
+    assert lib.pcpd_mlp_loss(None, None, None, None, 1, None, ctypes.byref(f)) == mod.PCPD_EINVAL

@@ -90,8 +90,10 @@ def _elementwise(a, b, scale, tag, bound=EXACT):
     return share, float(rel.max())
 
 
-@pytest.mark.parametrize("n", [128, 200, 777, 4096])
+@pytest.mark.parametrize("n", [128, 200, 777, 4096, 40000])
 def test_gradient_matches_oracle_elementwise(pcpd, n):
+    """n = 40000 is 625 tiles of 64 rows on the backward pass's 512
+    workgroups: some workgroups sum two tiles into their partial."""
     theta = _theta(2)
     x, t, m = _data(n, 10 + n)
     x = x.astype(np.float32).astype(np.float64)
@@ -208,3 +210,31 @@ def test_training_on_gpu_reduces_the_loss(pcpd):
     l1 = net.grads(xs, ts, ms)[0]
     print(f"[mlp train] loss {l0:.4f} -> {l1:.4f}", flush=True)
     assert l1 < 0.1 * l0
+
+
+def test_loss_call_and_row_limits(pcpd):
+    """pcpd_mlp_loss (forward only) returns the loss of pcpd_mlp_grads and the
+    oracle's, on more rows than a gradient call takes; a gradient call beyond
+    PCPD_MLP_MAX_TRAIN_ROWS is refused before any device work."""
+    theta = _theta(3)
+    n = 70000
+    x, t, m = _data(n, 77)
+    x = x.astype(np.float32).astype(np.float64)
+    t = t.astype(np.float32).astype(np.float64)
+    net = pcpd.Surrogate(seed=0)
+    try:
+        net.set_params(theta)
+        X, T, M = _cuda(x), _cuda(t), _cuda(m)
+        lf = net.loss(X, T, M)
+        lg, _ = net.grads(X, T, M)
+        rl, _ = mo.loss_and_grad(theta, x, t, m)
+        assert lf == lg
+        assert abs(lf - rl) <= 1e-5 * max(1.0, rl)
+        big = pcpd.MLP_MAX_TRAIN_ROWS + 1
+        xb = torch.zeros((big, 3), dtype=torch.float32, device="cuda")
+        tb = torch.zeros(big, dtype=torch.float32, device="cuda")
+        assert net.loss(xb, tb) >= 0.0          # forward-only calls take it
+        with pytest.raises(pcpd.PcpdError):
+            net.grads(xb, tb)
+    finally:
+        net.close()
