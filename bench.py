@@ -65,6 +65,9 @@ def parse():
                     help="tile width in blocks, halo included (0 = the library's default)")
     ap.add_argument("--phase-max", type=int, default=0,
                     help="most substeps per phase launch (0 = the library's default)")
+    ap.add_argument("--skip-empty", action="store_true",
+                    help="tiles with no particle in their loaded range skip their substeps "
+                         "(state-dependent rate; exact)")
     ap.add_argument("--persistent", action="store_true",
                     help="all phases between records in one ticket-dispatched launch")
     return ap.parse_args()
@@ -150,8 +153,8 @@ def main():
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
     if args.teams or args.tile_cols or args.phase_max:
         sim.set_tuning(args.tile_cols, args.phase_max, args.teams)
-    if args.persistent:
-        sim.set_options(persistent=True)
+    if args.persistent or args.skip_empty:
+        sim.set_options(persistent=args.persistent, skip_empty=args.skip_empty)
     if args.autotune:
         sim.autotune()
 
@@ -210,7 +213,8 @@ def main():
     config.update({"mc_steps_per_bench_step": M, "mc_steps_total": total_steps,
                    "records": "the workload's log-spaced record times, plus each step end",
                    "tile_cols": tuning[0], "phase_max": tuning[1], "teams": tuning[2],
-                   "persistent": args.persistent, "autotuned": args.autotune})
+                   "persistent": args.persistent, "skip_empty": args.skip_empty,
+                   "autotuned": args.autotune})
 
     out = {
         "metric": "site-updates/sec (samples x sites x MC steps) at 1 GPU",

@@ -211,9 +211,17 @@ typedef enum {
      * and more tiles than one phase fills). Results are identical. A dependency wait that
      * exceeds its bound (a correct run never does) stops the launch; the next synchronising
      * call returns PCPD_EDEVICE. With PCPD_OPT_GRAPH the persistent launches are captured. */
-    PCPD_OPT_PERSISTENT = 2
+    PCPD_OPT_PERSISTENT = 2,
+    /* Skip the substeps of a tile whose loaded range (interior and halo) holds no particle in
+     * any sample: no rule of eq. (1) acts on an empty window, so the tile ends the phase empty
+     * and only its zeros are written back. Results are identical; the time of a phase then
+     * depends on the state (late-time and extinct runs get cheaper), so rates measured with it
+     * are reported apart. */
+    PCPD_OPT_SKIP_EMPTY = 4
 } pcpd_option;
 
+/* Set the options (an OR of pcpd_option flags; unknown bits: PCPD_EINVAL). A change waits
+ * for the context's queued work and drops its captured graphs. */
 PCPD_API int pcpd_set_options(pcpd_ctx *ctx, uint32_t options);
 
 /* Pick the kernel shape by timing candidate tiles (blocks per tile x substeps

@@ -517,9 +517,10 @@ struct alignas(16) WordPair {
 // Copy `total` words of a tile, ring blocks kfirst, kfirst+1, ... (mod nb),
 // from HBM (natural order) into LDS column-per-block. Lane i handles words
 // i, i+nthr, ...; (column, row, ring block) advance incrementally.
+template <bool OR>
 __device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restrict__ ring,
                                           uint32_t kfirst, uint32_t nb, uint32_t total, uint32_t B,
-                                          uint32_t ldw, uint32_t tid, uint32_t nthr) {
+                                          uint32_t ldw, uint32_t tid, uint32_t nthr, uint64_t &any) {
     const uint32_t cstep = nthr / B, ostep = nthr - cstep * B, kstep = cstep % nb;
     uint32_t c = tid / B, o = tid - c * B;
     uint32_t kg = (kfirst + c) % nb;
@@ -542,7 +543,10 @@ __device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restr
         }
 #pragma unroll
         for (int u = 0; u < kCopyBatch; ++u)
-            if (i0 + u * nthr < total) lds[a[u]] = v[u];
+            if (i0 + u * nthr < total) {
+                lds[a[u]] = v[u];
+                if constexpr (OR) any |= v[u];
+            }
     }
 }
 
@@ -551,11 +555,11 @@ __device__ __forceinline__ void load_tile(uint64_t *lds, const uint64_t *__restr
 // 2*kCopyBatch*nthr words arrives in one round trip. FIXED_ROW: 2*nthr is a
 // multiple of B, so every pair of a lane lies in the same row (the default
 // shapes); the row-wrap test then drops out of the loop.
-template <bool FIXED_ROW>
+template <bool FIXED_ROW, bool OR>
 __device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *__restrict__ ring,
                                                 uint32_t kfirst, uint32_t nb, uint32_t total,
                                                 uint32_t B, uint32_t ldw, uint32_t tid,
-                                                uint32_t nthr) {
+                                                uint32_t nthr, uint64_t &any) {
     const WordPair *rp = reinterpret_cast<const WordPair *>(ring);
     const uint32_t step = 2u * nthr;
     const uint32_t cstep = step / B, ostep = step - cstep * B, kstep = cstep % nb;
@@ -586,8 +590,24 @@ __device__ __forceinline__ void load_tile_pairs(uint64_t *lds, const uint64_t *_
             if (i0 + u * step < total) {
                 lds[a[u]] = v[u].a;
                 lds[a[u] + ldw] = v[u].b;
+                if constexpr (OR) any |= v[u].a | v[u].b;
             }
     }
+}
+
+// The tile loaders by case; with OR, `any` collects the OR of every word
+// loaded by this lane.
+template <bool OR>
+__device__ __forceinline__ void load_tile_any(uint64_t *lds, const uint64_t *__restrict__ ring,
+                                              bool pairs, bool fixed_row, uint32_t kfirst,
+                                              uint32_t nb, uint32_t total, uint32_t B, uint32_t ldw,
+                                              uint32_t tid, uint32_t nthr, uint64_t &any) {
+    if (pairs && fixed_row)
+        load_tile_pairs<true, OR>(lds, ring, kfirst, nb, total, B, ldw, tid, nthr, any);
+    else if (pairs)
+        load_tile_pairs<false, OR>(lds, ring, kfirst, nb, total, B, ldw, tid, nthr, any);
+    else
+        load_tile<OR>(lds, ring, kfirst, nb, total, B, ldw, tid, nthr, any);
 }
 
 // Copy the interior columns hb .. hb+total/B-1 of the tile back to HBM, where
@@ -660,7 +680,7 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
                                            uint64_t *__restrict__ dst, const LatDesc &ld,
                                            const TileDesc &td, uint64_t s0, uint32_t S,
                                            uint32_t B, uint32_t hb, uint32_t cols,
-                                           uint32_t ldw_arg) {
+                                           uint32_t ldw_arg, bool skip_empty) {
     const uint32_t ldw = PITCH ? PITCH : ldw_arg;
     const uint32_t nb = ld.nblocks;
     const uint32_t ncols = td.kint + 2u * hb;
@@ -677,18 +697,35 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
 
     // ---- load tile + halo: consecutive lanes read consecutive words
     const bool fixed_row = (2u * nthr) % B == 0u;
-    if (pairs && fixed_row)
-        load_tile_pairs<true>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
-    else if (pairs)
-        load_tile_pairs<false>(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
-    else
-        load_tile(lds, src + ld.base, kfirst, nb, ncols * B, B, ldw, tid, nthr);
-    __syncthreads();
+    uint64_t any = 0;
+    // Empty-tile skip: no rule of the models creates a particle next to an
+    // empty window, so a tile whose loaded range (interior and halo) holds
+    // no particle in any of the 64 samples ends the phase empty as well; it
+    // writes its (zero) interior back without running the substeps. Exact:
+    // the draws of windows that meet no particle change nothing.
+    // The flag word after the tile says whether some wavefront loaded a
+    // particle: cleared before the loads, set after the first barrier, read
+    // after the second (no substep writes it).
+    bool empty = false;
+    if (skip_empty) {
+        uint32_t *flag = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw);
+        if (tid == 0) *flag = 0u;
+        load_tile_any<true>(lds, src + ld.base, pairs, fixed_row, kfirst, nb, ncols * B, B, ldw,
+                            tid, nthr, any);
+        __syncthreads();
+        if (__ballot(any != 0ull) != 0ull && (tid & 63u) == 0u) *flag = 1u;
+        __syncthreads();
+        empty = __builtin_amdgcn_readfirstlane(*flag) == 0u;
+    } else {
+        load_tile_any<false>(lds, src + ld.base, pairs, fixed_row, kfirst, nb, ncols * B, B, ldw,
+                             tid, nthr, any);
+        __syncthreads();
+    }
 
     // ---- connected layout: rotate the columns loaded from past the ends of
     // the word ring (only at a ring's first and last tiles, or in rings
     // shorter than the tile): front columns [0, lo_end), back [hi_start, ncols)
-    if (ld.connected) {
+    if (ld.connected && !empty) {
         const int64_t v0 = static_cast<int64_t>(td.k0) - hb;  // virtual block of column 0
         const uint32_t lo_end =
             v0 < 0 ? static_cast<uint32_t>(-v0 < static_cast<int64_t>(ncols) ? -v0 : ncols) : 0u;
@@ -707,7 +744,7 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
     }
 
     // ---- S substeps in LDS, one window (block) per lane
-    {
+    if (!empty) {
         // per is a multiple of the wavefront size, so the team is uniform
         // per wavefront and its branches stay on the scalar unit
         const uint32_t per = nthr / T;
@@ -745,7 +782,7 @@ __global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T,
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
           const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t B, uint32_t hb,
-          uint32_t cols, uint32_t ldw_arg) {
+          uint32_t cols, uint32_t ldw_arg, uint32_t skip_empty) {
     // first substep of the phase: the context's device clock plus this
     // launch's offset, so that a captured sequence of launches is valid at
     // any starting time
@@ -753,7 +790,7 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
     const TileDesc td = tiles[blockIdx.x];
     const LatDesc ld = lats[td.lat];
-    tile_phase<N, PITCH, T>(lds, src, dst, ld, td, s0, S, B, hb, cols, ldw_arg);
+    tile_phase<N, PITCH, T>(lds, src, dst, ld, td, s0, S, B, hb, cols, ldw_arg, skip_empty != 0u);
 }
 
 // ---- persistent sweep: every phase of a stretch in one launch --------------
@@ -789,7 +826,7 @@ brs_persistent(uint64_t *__restrict__ buf0, uint64_t *__restrict__ buf1,
                const uint64_t *__restrict__ clock, uint64_t s_off, uint32_t S, uint32_t S_last,
                uint32_t B, uint32_t hb, uint32_t cols, uint32_t ldw_arg,
                PersistState *__restrict__ state, uint32_t *__restrict__ done,
-               uint32_t spin_limit) {
+               uint32_t spin_limit, uint32_t skip_empty) {
     extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
     __shared__ uint32_t sh_item, sh_stop;
     const uint64_t clk = *clock;
@@ -862,7 +899,7 @@ brs_persistent(uint64_t *__restrict__ buf0, uint64_t *__restrict__ buf1,
         const uint64_t s0 = clk + s_off + static_cast<uint64_t>(f) * S;
         const uint32_t Sf = (f + 1u == nphases) ? S_last : S;
         tile_phase<N, PITCH, T>(lds, (f & 1u) ? buf1 : buf0, (f & 1u) ? buf0 : buf1, ld, td, s0,
-                                Sf, B, hb, cols, ldw_arg);
+                                Sf, B, hb, cols, ldw_arg, skip_empty != 0u);
         // Every wavefront waits until its own stores have reached the L2 (a
         // workgroup barrier alone does not wait for global stores); the lane
         // that publishes the item then writes the L2 back with one
@@ -900,7 +937,8 @@ hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats
         attr_set = true;
     }
     hipLaunchKernelGGL((brs_phase<N, PITCH, T>), dim3(ntiles), dim3(sh.threads), lds, stream,
-                       src, dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw);
+                       src, dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw,
+                       sh.skip_empty);
     return hipGetLastError();
 }
 
@@ -955,7 +993,7 @@ hipError_t launch_persist_kernel(const PersistLaunch &a, const PhaseShape &sh,
     hipLaunchKernelGGL(kernel, dim3(static_cast<uint32_t>(grid)), dim3(sh.threads), lds, stream,
                        a.buf0, a.buf1, a.lats, a.tiles, a.deps, a.ntiles, a.nphases, a.clock,
                        a.s_off, a.S, a.S_last, a.B, sh.hb, sh.cols, sh.ldw, a.state, a.done,
-                       a.spin_limit);
+                       a.spin_limit, sh.skip_empty);
     return hipGetLastError();
 }
 

@@ -372,6 +372,8 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
         (ctx->options & PCPD_OPT_PERSISTENT) && ctx->d_pstate &&
         pcpd::phase_lds_bytes(ctx->B, ctx->shape.ldw, ctx->phase_max) + pcpd::kPersistStaticLds <=
             pcpd::kMaxLdsBytes;
+    PhaseShape shape = ctx->shape;
+    shape.skip_empty = (ctx->options & PCPD_OPT_SKIP_EMPTY) ? 1u : 0u;
     for (const BatchOp &op : ops) {
         const uint64_t end = rel + op.steps * ctx->B;
         if (persistent && end > rel) {
@@ -401,7 +403,7 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
                 if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
                 if (e != hipSuccess) return e;
             }
-            hipError_t e = pcpd::launch_persist(ctx->n, a, ctx->shape, stream);
+            hipError_t e = pcpd::launch_persist(ctx->n, a, shape, stream);
             if (e == hipSuccess && ev) e = hipEventRecord(ev[1], stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ctx->h_abort, &ctx->d_pstate->abort, sizeof(uint32_t),
@@ -420,7 +422,7 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
             }
             hipError_t e = pcpd::launch_phase(ctx->n, ctx->buf[cur], ctx->buf[cur ^ 1], ctx->d_lats,
                                               ctx->d_tiles, ctx->ntiles, ctx->d_clock, rel, S,
-                                              ctx->B, ctx->shape, stream);
+                                              ctx->B, shape, stream);
             if (e == hipSuccess && ev) e = hipEventRecord(ev[1], stream);
             if (e != hipSuccess) return e;
             cur ^= 1;
@@ -920,9 +922,15 @@ int pcpd_get_tuning(pcpd_ctx *ctx, pcpd_tuning *tuning) {
 }
 
 int pcpd_set_options(pcpd_ctx *ctx, uint32_t options) {
-    if (!ctx || (options & ~static_cast<uint32_t>(PCPD_OPT_GRAPH | PCPD_OPT_PERSISTENT)))
-        return PCPD_EINVAL;
+    constexpr uint32_t known = PCPD_OPT_GRAPH | PCPD_OPT_PERSISTENT | PCPD_OPT_SKIP_EMPTY;
+    if (!ctx || (options & ~known)) return PCPD_EINVAL;
     if (ctx->broken) return PCPD_ESTATE;
+    if (options != ctx->options) {
+        // captured graphs hold the launches of the old options
+        hipError_t e = sync_checked(ctx);
+        if (e != hipSuccess) return fail(ctx, e);
+        drop_graphs(ctx);
+    }
     ctx->options = options;
     return PCPD_OK;
 }

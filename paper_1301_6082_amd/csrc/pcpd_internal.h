@@ -94,6 +94,7 @@ struct PhaseShape {
     uint32_t ldw;      // LDS row pitch in words (>= cols + 3, odd)
     uint32_t hb;       // halo blocks on each side
     uint32_t teams;    // lanes per block (2 or 4), each applying every teams-th substep
+    uint32_t skip_empty = 0;  // 1: tiles with no particle in their loaded range skip the substeps
 };
 
 // One phase: S substeps starting at substep *clock + s_off.
@@ -129,7 +130,7 @@ hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream
 hipError_t launch_density(const uint64_t *buf, const LatDesc *lats, const DenChunk *chunks,
                           uint32_t nchunks, Counts *out, uint32_t nlat, hipStream_t stream);
 
-// LDS of one phase workgroup: B x ldw lattice words and S local sites.
+// LDS of one phase workgroup: B x ldw lattice words and the empty-tile flag word.
 size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S);
 
 }  // namespace pcpd

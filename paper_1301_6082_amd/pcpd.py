@@ -18,7 +18,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpcpd.so")
 
-OPT_GRAPH, OPT_PERSISTENT = 1, 2
+OPT_GRAPH, OPT_PERSISTENT, OPT_SKIP_EMPTY = 1, 2, 4
 PCPD_OK, PCPD_EINVAL, PCPD_ENOMEM, PCPD_EDEVICE, PCPD_ESTATE, PCPD_EOVERFLOW = 0, -1, -2, -3, -4, -5
 PCPD_ELIMIT = -6
 NOALLOC_MAX_WORDS = 1 << 22
@@ -239,10 +239,12 @@ class Sim:
         _check(_lib.pcpd_get_tuning(self._ctx, ctypes.byref(tu)), "pcpd_get_tuning")
         return int(tu.tile_cols), int(tu.phase_max), int(tu.teams)
 
-    def set_options(self, graph: bool = False, persistent: bool = False):
+    def set_options(self, graph: bool = False, persistent: bool = False, skip_empty: bool = False):
         """graph=True: capture sweep segments into HIP graphs and replay them;
-        persistent=True: all phases between two records in one ticket-dispatched launch."""
-        flags = (OPT_GRAPH if graph else 0) | (OPT_PERSISTENT if persistent else 0)
+        persistent=True: all phases between two records in one ticket-dispatched launch;
+        skip_empty=True: tiles with no particle in their loaded range skip their substeps."""
+        flags = ((OPT_GRAPH if graph else 0) | (OPT_PERSISTENT if persistent else 0) |
+                 (OPT_SKIP_EMPTY if skip_empty else 0))
         _check(_lib.pcpd_set_options(self._ctx, flags), "pcpd_set_options", self._ctx)
 
     def autotune(self, reps: int = 3):

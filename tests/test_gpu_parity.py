@@ -392,3 +392,66 @@ def test_connected_layout_persistent_and_graph(pcpd):
                   options={"persistent": True}, layout=1)
     _compare_full(pcpd, 2, 64, 2, 4, insts, [2, 40], tuning=(128, 4, 2),
                   options={"graph": True}, layout=1)
+
+
+# ---- empty-tile skip ------------------------------------------------------------
+
+def _clustered(L, planes, centres, width, seed):
+    """Host start: all words empty except random words in a few clusters (so
+    that some tiles of a phase hold particles and the rest do not)."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros(planes * L, dtype=np.uint64)
+    for q in range(planes):
+        for c in centres:
+            lo = q * L + (c % L)
+            for j in range(width):
+                w[q * L + (c + j) % L] = rng.integers(0, 1 << 63, dtype=np.uint64) | np.uint64(1)
+    return w
+
+
+@pytest.mark.parametrize("model", [1, 2, 3])
+@pytest.mark.parametrize("shape", [(128, 128, 2), (64, 16, 4), (40, 7, 2)])
+def test_skip_empty_tiles_matches_oracle(pcpd, model, shape):
+    """Sparse states: particles in a few clusters of a long ring, empty tiles
+    in between that the clusters grow into; every record and the final lattice
+    bit-exact against the oracle with empty tiles skipped."""
+    L = 64 * 900
+    start = _clustered(L, 2, [100, 20000, 40000 + 33, L - 10], 12, 5)
+    insts = [Instance(0.1, 0.5, L, 2, wl.INIT_HOST, start),
+             Instance(0.25, 0.2, L, 3, wl.INIT_HOST, start),
+             Instance(0.1, 0.5, 64 * 5, 4, wl.INIT_EMPTY)]
+    _compare_full(pcpd, model, 64, 2, 9, insts, [1, 2, 5, 12], tuning=shape,
+                  options={"skip_empty": True})
+
+
+def test_skip_empty_tiles_through_extinction(pcpd):
+    """Small rings deep in the absorbing phase die out; from then on every
+    tile is skipped, before that only some. Direct, persistent and graph
+    launches, and the connected layout."""
+    insts = [Instance(0.6, 0.1, 64 * 12, k) for k in range(6)] + \
+            [Instance(0.3, 0.5, 64 * 300, 7), Instance(0.9, 0.05, 64 * 40, 8)]
+    times = [1, 4, 16, 64, 200]
+    _compare_full(pcpd, 2, 64, 1, 3, insts, times, options={"skip_empty": True})
+    _compare_full(pcpd, 2, 64, 1, 3, insts, times, tuning=(64, 32, 2),
+                  options={"skip_empty": True, "persistent": True})
+    _compare_full(pcpd, 2, 64, 1, 3, insts, times, options={"skip_empty": True, "graph": True})
+    _compare_full(pcpd, 2, 64, 1, 3, insts, times, options={"skip_empty": True}, layout=1)
+
+
+def test_skip_option_change_drops_graphs(pcpd):
+    """Options switched between runs of one context (graphs captured before
+    the change are not replayed after it): the trajectory is the oracle's."""
+    L = 64 * 300
+    start = _clustered(L, 1, [50, 9000], 20, 8)
+    insts = [Instance(0.2, 0.4, L, 1, wl.INIT_HOST, start)]
+    with pcpd.Sim(2, 64, 1, 6, insts) as sim:
+        sim.set_tuning(64, 8, 2)
+        sim.set_options(graph=True)
+        sim.sweep(40)
+        sim.set_options(graph=True, skip_empty=True)
+        sim.sweep(40)
+        sim.set_options(skip_empty=True)
+        sim.sweep(7)
+        got = sim.get_lattice(0)
+    _, runs = oracle_runs(2, 64, 1, 6, insts, [87])
+    np.testing.assert_array_equal(got, runs[0].words)
