@@ -9,15 +9,19 @@ end; consecutive steps continue the same trajectory, so warmup + timed steps
 cover a prefix of the 10^5-step run.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mc-per-step M]
-                    [--workload cfg2|cfg3|cfg4] [--autotune]
+                    [--workload cfg2|cfg3|cfg4|dp_absorbing] [--autotune]
+                    [--tile-cols C] [--phase-max S] [--teams T] [--persistent]
+                    [--skip-empty]
 
 Prints one JSON line. Also reports the dominant kernel (the phase kernel of
 the sweep) against the integer-VALU roofline, and the CPU oracle on a bounded
 sample of the same workload. The default workload is the one above; cfg3 (512
-batched PCPD rings of uneven length, one plane) and cfg4 (TCPD, 8 rings of
-2^18 sites, one plane) report the same metric on those workloads, without the
+batched PCPD rings of uneven length, one plane), cfg4 (TCPD, 8 rings of 2^18
+sites, one plane) and dp_absorbing (DP, 16 rings of 2^18 sites across the
+absorbing transition) report the same metric on those workloads, without the
 CPU leg. --autotune times the library's tile shapes on the workload before the
-timed region.
+timed region; --skip-empty skips tiles with no particle (exact; the rate then
+depends on the state, so it is reported apart).
 """
 from __future__ import annotations
 
@@ -56,7 +60,7 @@ def parse():
                     help="(instance, plane) units for the oracle timing; 0 = one per host thread")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="copy 1 GiB device-to-device three times first (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg2", "cfg3", "cfg4"), default="cfg2")
+    ap.add_argument("--workload", choices=("cfg2", "cfg3", "cfg4", "dp_absorbing"), default="cfg2")
     ap.add_argument("--autotune", action="store_true",
                     help="time the library's tile shapes on the workload first (untimed)")
     ap.add_argument("--teams", type=int, default=0, choices=(0, 2, 4),
@@ -137,7 +141,8 @@ def main():
     torch.cuda.set_device(0)
     M = args.mc_per_step
     total_steps = (args.warmup + args.steps) * M
-    wl = {"cfg2": workloads.cfg2, "cfg3": workloads.cfg3, "cfg4": workloads.cfg4}[args.workload]()
+    wl = {"cfg2": workloads.cfg2, "cfg3": workloads.cfg3, "cfg4": workloads.cfg4,
+          "dp_absorbing": workloads.dp_absorbing}[args.workload]()
     rec_times = [t for t in wl.times]
     su_per_mc = sum(64 * wl.planes * inst.L for inst in wl.instances)
 

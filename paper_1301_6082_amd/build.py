@@ -13,8 +13,11 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpcpd.so")
-SOURCES = ["phase_n1.hip", "phase_n2.hip", "phase_n3.hip", "phase_n4.hip", "sweep.hip",
-           "pcpd_api.hip", "mlp.hip"]
+# the kernel translation units, longest to compile first (PCPD has the extra
+# copy compiled for its default pitch)
+SOURCES = ["phase_n2.hip", "persist_n2.hip", "phase_n1.hip", "phase_n3.hip", "phase_n4.hip",
+           "persist_n1.hip", "persist_n3.hip", "persist_n4.hip", "mlp.hip", "pcpd_api.hip",
+           "sweep.hip"]
 BUILD_DIR = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 

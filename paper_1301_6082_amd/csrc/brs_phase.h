@@ -675,7 +675,10 @@ constexpr uint32_t kDefaultPitch = 131;
 // One tile for one phase: load the tile and its halo from `src` into LDS,
 // run S substeps starting at substep s0, write the interior to `dst`. T
 // lanes per block (the T teams).
-template <int N, uint32_t PITCH, int T>
+// GENERAL: the copy of the kernel that also handles the connected layout and
+// the empty-tile skip; the other copy (the default) compiles the classical
+// path alone, so that neither feature costs it anything.
+template <int N, uint32_t PITCH, int T, bool GENERAL>
 __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__restrict__ src,
                                            uint64_t *__restrict__ dst, const LatDesc &ld,
                                            const TileDesc &td, uint64_t s0, uint32_t S,
@@ -707,7 +710,7 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
     // particle: cleared before the loads, set after the first barrier, read
     // after the second (no substep writes it).
     bool empty = false;
-    if (skip_empty) {
+    if (GENERAL && skip_empty) {
         uint32_t *flag = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw);
         if (tid == 0) *flag = 0u;
         load_tile_any<true>(lds, src + ld.base, pairs, fixed_row, kfirst, nb, ncols * B, B, ldw,
@@ -725,21 +728,24 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
     // ---- connected layout: rotate the columns loaded from past the ends of
     // the word ring (only at a ring's first and last tiles, or in rings
     // shorter than the tile): front columns [0, lo_end), back [hi_start, ncols)
-    if (ld.connected && !empty) {
-        const int64_t v0 = static_cast<int64_t>(td.k0) - hb;  // virtual block of column 0
-        const uint32_t lo_end =
-            v0 < 0 ? static_cast<uint32_t>(-v0 < static_cast<int64_t>(ncols) ? -v0 : ncols) : 0u;
-        const int64_t hs = static_cast<int64_t>(nb) - v0;
-        const uint32_t hi_start = hs <= 0 ? 0u : (hs >= ncols ? ncols : static_cast<uint32_t>(hs));
-        const uint32_t nout = lo_end >= hi_start ? ncols : lo_end + (ncols - hi_start);
-        if (nout > 0u) {
-            for (uint32_t i = tid; i < nout * B; i += nthr) {
-                const uint32_t idx = i / B, o = i - idx * B;
-                const uint32_t c = lo_end >= hi_start ? idx : (idx < lo_end ? idx : hi_start + idx - lo_end);
-                const int32_t m = ring_lap(v0 + c, nb);
-                if (m != 0) lds[o * ldw + c] = rotr64(lds[o * ldw + c], m);
+    if constexpr (GENERAL) {
+        if (ld.connected && !empty) {
+            const int64_t v0 = static_cast<int64_t>(td.k0) - hb;  // virtual block of column 0
+            const uint32_t lo_end =
+                v0 < 0 ? static_cast<uint32_t>(-v0 < static_cast<int64_t>(ncols) ? -v0 : ncols) : 0u;
+            const int64_t hs = static_cast<int64_t>(nb) - v0;
+            const uint32_t hi_start = hs <= 0 ? 0u : (hs >= ncols ? ncols : static_cast<uint32_t>(hs));
+            const uint32_t nout = lo_end >= hi_start ? ncols : lo_end + (ncols - hi_start);
+            if (nout > 0u) {
+                for (uint32_t i = tid; i < nout * B; i += nthr) {
+                    const uint32_t idx = i / B, o = i - idx * B;
+                    const uint32_t c =
+                        lo_end >= hi_start ? idx : (idx < lo_end ? idx : hi_start + idx - lo_end);
+                    const int32_t m = ring_lap(v0 + c, nb);
+                    if (m != 0) lds[o * ldw + c] = rotr64(lds[o * ldw + c], m);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 
@@ -753,10 +759,16 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
         const uint32_t trash = cols + 1u;  // spare columns cols .. cols+2
         uint32_t kb = kfirst + c;
         if (kb >= nb) kb %= nb;
-        const int64_t v0 = static_cast<int64_t>(td.k0) - hb;
-        if (ld.connected && (v0 < 0 || v0 + static_cast<int64_t>(ncols) > static_cast<int64_t>(nb))) {
-            const uint32_t rot = c < ncols ? static_cast<uint32_t>(ring_lap(v0 + c, nb)) & 63u : 0u;
-            dispatch_kd<N, T>(lds, ld, LapWin{kb, rot}, c, team, ncols, trash, s0, S, B, ldw);
+        if constexpr (GENERAL) {
+            const int64_t v0 = static_cast<int64_t>(td.k0) - hb;
+            if (ld.connected &&
+                (v0 < 0 || v0 + static_cast<int64_t>(ncols) > static_cast<int64_t>(nb))) {
+                const uint32_t rot =
+                    c < ncols ? static_cast<uint32_t>(ring_lap(v0 + c, nb)) & 63u : 0u;
+                dispatch_kd<N, T>(lds, ld, LapWin{kb, rot}, c, team, ncols, trash, s0, S, B, ldw);
+            } else {
+                dispatch_kd<N, T>(lds, ld, PlainWin{kb, 0u}, c, team, ncols, trash, s0, S, B, ldw);
+            }
         } else {
             dispatch_kd<N, T>(lds, ld, PlainWin{kb, 0u}, c, team, ncols, trash, s0, S, B, ldw);
         }
@@ -777,7 +789,7 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
 // SIMD. PITCH is the LDS row pitch as a compile-time constant (0: the ldw_arg
 // argument); with a constant pitch the rows of a window are immediate offsets
 // from one address.
-template <int N, uint32_t PITCH, int T>
+template <int N, uint32_t PITCH, int T, bool GENERAL>
 __global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
 brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
           const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
@@ -790,7 +802,8 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
     extern __shared__ uint64_t lds[];  // [B][ldw] lattice words
     const TileDesc td = tiles[blockIdx.x];
     const LatDesc ld = lats[td.lat];
-    tile_phase<N, PITCH, T>(lds, src, dst, ld, td, s0, S, B, hb, cols, ldw_arg, skip_empty != 0u);
+    tile_phase<N, PITCH, T, GENERAL>(lds, src, dst, ld, td, s0, S, B, hb, cols, ldw_arg,
+                                     skip_empty != 0u);
 }
 
 // ---- persistent sweep: every phase of a stretch in one launch --------------
@@ -818,7 +831,7 @@ brs_phase(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst,
 // workgroup stops (the host reports a device error); a correct schedule never
 // comes near the limit.
 
-template <int N, uint32_t PITCH, int T>
+template <int N, uint32_t PITCH, int T, bool GENERAL>
 __global__ void __launch_bounds__(256 * T) __attribute__((amdgpu_waves_per_eu(T, T)))
 brs_persistent(uint64_t *__restrict__ buf0, uint64_t *__restrict__ buf1,
                const LatDesc *__restrict__ lats, const TileDesc *__restrict__ tiles,
@@ -898,7 +911,7 @@ brs_persistent(uint64_t *__restrict__ buf0, uint64_t *__restrict__ buf1,
         const LatDesc ld = lats[td.lat];
         const uint64_t s0 = clk + s_off + static_cast<uint64_t>(f) * S;
         const uint32_t Sf = (f + 1u == nphases) ? S_last : S;
-        tile_phase<N, PITCH, T>(lds, (f & 1u) ? buf1 : buf0, (f & 1u) ? buf0 : buf1, ld, td, s0,
+        tile_phase<N, PITCH, T, GENERAL>(lds, (f & 1u) ? buf1 : buf0, (f & 1u) ? buf0 : buf1, ld, td, s0,
                                 Sf, B, hb, cols, ldw_arg, skip_empty != 0u);
         // Every wavefront waits until its own stores have reached the L2 (a
         // workgroup barrier alone does not wait for global stores); the lane
@@ -922,7 +935,7 @@ __global__ void persist_reset(PersistState *__restrict__ state, uint32_t *__rest
     for (uint32_t j = i; j < ntiles; j += gridDim.x * blockDim.x) done[j] = 0u;
 }
 
-template <int N, uint32_t PITCH, int T>
+template <int N, uint32_t PITCH, int T, bool GENERAL>
 hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                          const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
                          uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
@@ -930,13 +943,13 @@ hipError_t launch_kernel(const uint64_t *src, uint64_t *dst, const LatDesc *lats
     const size_t lds = phase_lds_bytes(B, sh.ldw, S);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH, T>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&brs_phase<N, PITCH, T, GENERAL>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(kMaxLdsBytes));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((brs_phase<N, PITCH, T>), dim3(ntiles), dim3(sh.threads), lds, stream,
+    hipLaunchKernelGGL((brs_phase<N, PITCH, T, GENERAL>), dim3(ntiles), dim3(sh.threads), lds, stream,
                        src, dst, lats, tiles, clock, s_off, S, B, sh.hb, sh.cols, sh.ldw,
                        sh.skip_empty);
     return hipGetLastError();
@@ -947,18 +960,22 @@ hipError_t launch_teams(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                         const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,
                         uint64_t s_off, uint32_t S, uint32_t B, const PhaseShape &sh,
                         hipStream_t stream) {
+    if (sh.general)
+        return launch_kernel<N, 0, T, true>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh,
+                                            stream);
     if constexpr (N == 2) {
         if (sh.ldw == kDefaultPitch)
-            return launch_kernel<N, kDefaultPitch, T>(src, dst, lats, tiles, ntiles, clock, s_off,
-                                                      S, B, sh, stream);
+            return launch_kernel<N, kDefaultPitch, T, false>(src, dst, lats, tiles, ntiles, clock,
+                                                             s_off, S, B, sh, stream);
     }
-    return launch_kernel<N, 0, T>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh, stream);
+    return launch_kernel<N, 0, T, false>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, sh,
+                                         stream);
 }
 
-template <int N, uint32_t PITCH, int T>
+template <int N, uint32_t PITCH, int T, bool GENERAL>
 hipError_t launch_persist_kernel(const PersistLaunch &a, const PhaseShape &sh,
                                  hipStream_t stream) {
-    auto kernel = &brs_persistent<N, PITCH, T>;
+    auto kernel = &brs_persistent<N, PITCH, T, GENERAL>;
     const size_t lds = phase_lds_bytes(a.B, sh.ldw, a.S);
     if (lds + kPersistStaticLds > kMaxLdsBytes) return hipErrorInvalidValue;
     static bool attr_set = false;
@@ -999,10 +1016,12 @@ hipError_t launch_persist_kernel(const PersistLaunch &a, const PhaseShape &sh,
 
 template <int N, int T>
 hipError_t launch_persist_teams(const PersistLaunch &a, const PhaseShape &sh, hipStream_t stream) {
+    if (sh.general) return launch_persist_kernel<N, 0, T, true>(a, sh, stream);
     if constexpr (N == 2) {
-        if (sh.ldw == kDefaultPitch) return launch_persist_kernel<N, kDefaultPitch, T>(a, sh, stream);
+        if (sh.ldw == kDefaultPitch)
+            return launch_persist_kernel<N, kDefaultPitch, T, false>(a, sh, stream);
     }
-    return launch_persist_kernel<N, 0, T>(a, sh, stream);
+    return launch_persist_kernel<N, 0, T, false>(a, sh, stream);
 }
 
 template <int N>
@@ -1017,7 +1036,8 @@ hipError_t launch_persist_n(const PersistLaunch &a, const PhaseShape &sh, hipStr
 
 // The default PCPD tile runs a copy of the kernel compiled for its pitch;
 // every other model and shape takes the pitch as an argument. Two or four
-// teams per tile.
+// teams per tile. Contexts with the connected layout or the empty-tile skip
+// run the general copy (pitch as an argument).
 template <int N>
 hipError_t launch_phase_n(const uint64_t *src, uint64_t *dst, const LatDesc *lats,
                           const TileDesc *tiles, uint32_t ntiles, const uint64_t *clock,

@@ -38,6 +38,7 @@ struct pcpd_ctx {
     std::vector<uint64_t> inst_base; // word offset of instance i's first plane
     uint64_t total_words = 0;        // planes * sum L
     uint32_t nlat = 0;               // n_inst * planes
+    bool connected = false;          // connected multispin layout (pcpd_config.layout)
 
     hipStream_t stream = nullptr;
     uint64_t *buf[2] = {nullptr, nullptr};
@@ -374,6 +375,7 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
             pcpd::kMaxLdsBytes;
     PhaseShape shape = ctx->shape;
     shape.skip_empty = (ctx->options & PCPD_OPT_SKIP_EMPTY) ? 1u : 0u;
+    shape.general = (shape.skip_empty || ctx->connected) ? 1u : 0u;
     for (const BatchOp &op : ops) {
         const uint64_t end = rel + op.steps * ctx->B;
         if (persistent && end > rel) {
@@ -614,6 +616,9 @@ hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t
                 !make_shape(static_cast<uint32_t>(ctx->n), B, cols, pm, teams, &sh))
                 continue;
             ctx->shape = sh;
+            // time the kernel copy the context's runs will use
+            sh.skip_empty = (ctx->options & PCPD_OPT_SKIP_EMPTY) ? 1u : 0u;
+            sh.general = (sh.skip_empty || ctx->connected) ? 1u : 0u;
             ctx->phase_max = pm;
             if ((e = build_tiles(ctx)) != hipSuccess) break;
             float ms = 0.0f;
@@ -734,6 +739,7 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
     pcpd_ctx *ctx = new (std::nothrow) pcpd_ctx();
     if (!ctx) return PCPD_ENOMEM;
     ctx->n = cfg->model;
+    ctx->connected = cfg->layout == PCPD_LAYOUT_CONNECTED;
     ctx->B = cfg->B;
     ctx->planes = cfg->planes;
     ctx->seed = cfg->seed;
@@ -1049,6 +1055,7 @@ int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t
     c.d_clock = reinterpret_cast<uint64_t *>(ws + kNaOffClock);
     c.shape = shape;
     c.phase_max = pmax;
+    c.connected = cfg->layout == PCPD_LAYOUT_CONNECTED;
 
     // The host tables are read by the copies before this call returns (it
     // synchronises below). Every count record is cleared by a kernel before

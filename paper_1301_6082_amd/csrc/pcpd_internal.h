@@ -95,6 +95,7 @@ struct PhaseShape {
     uint32_t hb;       // halo blocks on each side
     uint32_t teams;    // lanes per block (2 or 4), each applying every teams-th substep
     uint32_t skip_empty = 0;  // 1: tiles with no particle in their loaded range skip the substeps
+    uint32_t general = 0;     // 1: run the kernel copy with the connected layout and the skip
 };
 
 // One phase: S substeps starting at substep *clock + s_off.

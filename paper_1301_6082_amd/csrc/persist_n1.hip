@@ -1,0 +1,14 @@
+// persist_n1.hip -- the persistent sweep kernel for DP (n = 1), in a
+// translation unit of its own so that it compiles in parallel with the
+// per-phase kernel of the model (phase_n1.hip).
+
+#include "brs_phase.h"
+
+namespace pcpd {
+
+hipError_t launch_persist_model1(const PersistLaunch &a, const PhaseShape &shape,
+                                  hipStream_t stream) {
+    return launch_persist_n<1>(a, shape, stream);
+}
+
+}  // namespace pcpd

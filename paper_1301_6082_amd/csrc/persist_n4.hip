@@ -1,0 +1,14 @@
+// persist_n4.hip -- the persistent sweep kernel for QCPD (n = 4), in a
+// translation unit of its own so that it compiles in parallel with the
+// per-phase kernel of the model (phase_n4.hip).
+
+#include "brs_phase.h"
+
+namespace pcpd {
+
+hipError_t launch_persist_model4(const PersistLaunch &a, const PhaseShape &shape,
+                                  hipStream_t stream) {
+    return launch_persist_n<4>(a, shape, stream);
+}
+
+}  // namespace pcpd

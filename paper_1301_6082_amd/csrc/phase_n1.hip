@@ -12,9 +12,4 @@ hipError_t launch_phase_model1(const uint64_t *src, uint64_t *dst, const LatDesc
     return launch_phase_n<1>(src, dst, lats, tiles, ntiles, clock, s_off, S, B, shape, stream);
 }
 
-hipError_t launch_persist_model1(const PersistLaunch &a, const PhaseShape &shape,
-                                  hipStream_t stream) {
-    return launch_persist_n<1>(a, shape, stream);
-}
-
 }  // namespace pcpd

@@ -98,6 +98,17 @@ def cfg4(steps: int = 100_000) -> Workload:
     return Workload("tcpd_L2^18_8p_d0.5", TCPD, 64, 1, 1, inst, steps, log_times(steps))
 
 
+def dp_absorbing(steps: int = 100_000) -> Workload:
+    """DP (n = 1) rings of 2^18 sites, one plane, d = 0.5, 16 values of
+    p = linspace(0.05, 0.6, 16), fully occupied start: the rings deep in the
+    absorbing phase die out in every sample (the empty lattice is DP's only
+    absorbing state), the others stay active. For rates with empty tiles
+    skipped, which depend on the state."""
+    ps = np.linspace(0.05, 0.6, 16)
+    inst = [Instance(float(p), 0.5, 1 << 18, i) for i, p in enumerate(ps)]
+    return Workload("dp_L2^18_16p_d0.5", DP, 64, 1, 1, inst, steps, log_times(steps))
+
+
 def random_lattice(L: int, planes: int, density: float, seed: int) -> np.ndarray:
     """planes*L uint64 words with each bit set independently with `density`."""
     rng = np.random.default_rng(seed)
