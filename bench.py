@@ -11,7 +11,7 @@ cover a prefix of the 10^5-step run.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mc-per-step M]
                     [--workload cfg2|cfg3|cfg4|dp_absorbing] [--autotune]
                     [--tile-cols C] [--phase-max S] [--teams T] [--persistent]
-                    [--skip-empty]
+                    [--skip-empty] [--graph]
 
 Prints one JSON line. Also reports the dominant kernel (the phase kernel of
 the sweep) against the integer-VALU roofline, and the CPU oracle on a bounded
@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--skip-empty", action="store_true",
                     help="tiles with no particle in their loaded range skip their substeps "
                          "(state-dependent rate; exact)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured HIP graphs in the timed region (profiling off there); "
+                         "the kernel time comes from one more, profiled step after it")
     ap.add_argument("--persistent", action="store_true",
                     help="all phases between records in one ticket-dispatched launch")
     return ap.parse_args()
@@ -158,8 +161,8 @@ def main():
     sim = pcpd.Sim(wl.model, wl.B, wl.planes, wl.seed, wl.instances)
     if args.teams or args.tile_cols or args.phase_max:
         sim.set_tuning(args.tile_cols, args.phase_max, args.teams)
-    if args.persistent or args.skip_empty:
-        sim.set_options(persistent=args.persistent, skip_empty=args.skip_empty)
+    if args.persistent or args.skip_empty or args.graph:
+        sim.set_options(graph=args.graph, persistent=args.persistent, skip_empty=args.skip_empty)
     if args.autotune:
         sim.autotune()
 
@@ -173,8 +176,11 @@ def main():
     torch.cuda.synchronize()
 
     # the dominant kernel (the sweep's phase kernel) is timed by HIP events
-    # that the library records around each launch on its own stream
-    sim.profile(True)
+    # that the library records around each launch on its own stream; with
+    # --graph the timed region replays graphs unprofiled (profiling launches
+    # directly), and one more step after it is profiled instead
+    if not args.graph:
+        sim.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     counts = None
@@ -182,14 +188,21 @@ def main():
         counts = sim.run(step_times(k))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    assert sim.time == total_steps
+    if args.graph:
+        sim.profile(True)
+        sim.run(step_times(args.warmup + args.steps))
+        torch.cuda.synchronize()
     kernel_ms, launches = sim.profile_read()
     sim.profile(False)
-    assert sim.time == total_steps
     site_updates = su_per_mc * M * args.steps
     value = site_updates / elapsed
 
     tuning = sim.get_tuning()
     launch_ms = kernel_ms / launches
+    if args.graph:   # the timed steps' launches at the profiled step's rate
+        launches = launches * args.steps
+        kernel_ms = launch_ms * launches
     word_updates = site_updates / 64          # interior windows, all launches
     ops_word = OPS_PER_WORD_UPDATE[wl.model]
     ops_per_launch = ops_word * word_updates / launches
@@ -219,6 +232,7 @@ def main():
                    "records": "the workload's log-spaced record times, plus each step end",
                    "tile_cols": tuning[0], "phase_max": tuning[1], "teams": tuning[2],
                    "persistent": args.persistent, "skip_empty": args.skip_empty,
+                   "graph": args.graph,
                    "autotuned": args.autotune})
 
     out = {

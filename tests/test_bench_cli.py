@@ -27,4 +27,5 @@ def test_defaults():
         (1, 30, 2, 1000, "cfg2", False)
     assert bench.OPS_PER_WORD_UPDATE == {1: 129, 2: 131, 3: 135, 4: 139}
     # the default line runs the library's default shape, per-phase launches, no skipping
-    assert (a.teams, a.tile_cols, a.phase_max, a.persistent, a.skip_empty) == (0, 0, 0, False, False)
+    assert (a.teams, a.tile_cols, a.phase_max, a.persistent, a.skip_empty, a.graph) == \
+        (0, 0, 0, False, False, False)
