@@ -225,11 +225,17 @@ typedef enum {
 PCPD_API int pcpd_set_options(pcpd_ctx *ctx, uint32_t options);
 
 /* Pick the kernel shape by timing candidate tiles (blocks per tile x substeps
- * per phase) on this context's own lattice: each trial reads the current copy
- * and writes the spare one, so the state is unchanged. `reps` timed launches
+ * per phase x teams) on this context's own lattice: each trial reads the current
+ * copy and writes the spare one, so the state is unchanged. `reps` timed launches
  * per candidate (0 = 3). The choice is cached per process for contexts of the
  * same model, block width and ring sizes, applied to the context and returned
- * in *chosen (may be NULL). Results never depend on the shape. */
+ * in *chosen (may be NULL). Results never depend on the shape.
+ * On disk: if the environment variable PCPD_TUNE_CACHE names a file, an entry
+ * there for this GPU architecture and key is used without timing (the last
+ * matching line wins; an entry written by hand forces a shape), and a shape
+ * that had to be timed is appended. A line holds the architecture (e.g.
+ * gfx950), model n, B, the number of rings, their total, largest and smallest
+ * block counts, then tile columns, substeps per phase and teams. */
 PCPD_API int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen);
 
 /* Timing of the sweep's phase kernels: while enabled, every phase launch is

@@ -8,10 +8,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/pcpd.h"
@@ -587,6 +590,61 @@ std::map<TuneKey, std::pair<PhaseShape, uint32_t>> &tune_cache() {
     return cache;
 }
 
+// On-disk tuning cache: when the environment variable PCPD_TUNE_CACHE names a
+// file, pcpd_autotune first looks the context up there (by GPU architecture
+// and the key above) and appends what it measures otherwise. One entry per
+// line: arch, the key's six numbers, then tile columns, phase length, teams.
+// An entry may also be written by hand to force a shape; every shape gives
+// the same results, and an entry the library cannot build is ignored.
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool disk_lookup(const char *path, const std::string &arch, const TuneKey &key, uint32_t n,
+                 uint32_t B, PhaseShape *shape, uint32_t *pm) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char a[128];
+        unsigned long long k[6];
+        unsigned cols, phase, teams;
+        if (std::sscanf(line, "%127s %llu %llu %llu %llu %llu %llu %u %u %u", a, &k[0], &k[1], &k[2],
+                        &k[3], &k[4], &k[5], &cols, &phase, &teams) != 10)
+            continue;
+        if (arch != a || key.size() != 6) continue;
+        bool same = true;
+        for (int i = 0; i < 6; ++i) same = same && key[i] == k[i];
+        PhaseShape sh{};
+        if (same && make_shape(n, B, cols, phase, teams, &sh)) {
+            *shape = sh;
+            *pm = phase;
+            found = true;  // the last matching entry wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void disk_append(const char *path, const std::string &arch, const TuneKey &key,
+                 const PhaseShape &shape, uint32_t pm) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s", arch.c_str());
+    for (uint64_t v : key) std::fprintf(f, " %llu", static_cast<unsigned long long>(v));
+    std::fprintf(f, " %u %u %u\n", shape.cols, pm, shape.teams);
+    std::fclose(f);
+}
+
 // Time one phase launch of each candidate shape on the context's own lattice:
 // it reads the current copy and writes the spare one, so the state is left
 // untouched. Cost = kernel time per interior window-substep.
@@ -946,16 +1004,22 @@ int pcpd_autotune(pcpd_ctx *ctx, uint32_t reps, pcpd_tuning *chosen) {
     if (ctx->broken) return PCPD_ESTATE;
     if (reps == 0) reps = 3;
     TuneKey key = tune_key(ctx);
-    auto hit = tune_cache().find(key);
     PhaseShape best{};
     uint32_t best_pm = 0;
-    if (hit != tune_cache().end()) {
+    const char *path = std::getenv("PCPD_TUNE_CACHE");
+    const std::string arch = path ? device_arch() : std::string();
+    auto hit = tune_cache().find(key);
+    if (path && *path &&
+        disk_lookup(path, arch, key, static_cast<uint32_t>(ctx->n), ctx->B, &best, &best_pm)) {
+        tune_cache()[key] = {best, best_pm};
+    } else if (hit != tune_cache().end()) {
         best = hit->second.first;
         best_pm = hit->second.second;
     } else {
         hipError_t e = search_shape(ctx, reps, &best, &best_pm);
         if (e != hipSuccess) return fail(ctx, e);
         tune_cache()[key] = {best, best_pm};
+        if (path && *path) disk_append(path, arch, key, best, best_pm);
     }
     hipError_t e = sync_checked(ctx);
     if (e != hipSuccess) return fail(ctx, e);

@@ -455,3 +455,30 @@ def test_skip_option_change_drops_graphs(pcpd):
         got = sim.get_lattice(0)
     _, runs = oracle_runs(2, 64, 1, 6, insts, [87])
     np.testing.assert_array_equal(got, runs[0].words)
+
+
+def test_autotune_disk_cache_and_forced_shape(pcpd, tmp_path, monkeypatch):
+    """PCPD_TUNE_CACHE: a hand-written entry for this lattice forces its shape
+    (no timing), the run matches the oracle; a lattice without an entry is
+    timed and appended to the file."""
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    insts = [Instance(0.12, 0.4, 64 * 1300, 3), Instance(0.2, 0.1, 64 * 700, 4)]
+    nb = [i.L // 64 for i in insts]
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{arch} 2 64 2 {sum(nb)} {max(nb)} {min(nb)} 96 48 4\n")
+    monkeypatch.setenv("PCPD_TUNE_CACHE", str(cache))
+    with pcpd.Sim(2, 64, 1, 11, insts) as sim:
+        assert sim.autotune(reps=1) == (96, 48, 4)
+        assert sim.get_tuning() == (96, 48, 4)
+        sim.run([5])
+        lat = [sim.get_lattice(i) for i in range(2)]
+    keys, runs = oracle_runs(2, 64, 1, 11, insts, [5])
+    for (i, q), r in zip(keys, runs):
+        np.testing.assert_array_equal(lat[i], r.words)
+    other = [Instance(0.1, 0.5, 64 * 333, 0)]
+    with pcpd.Sim(2, 64, 1, 1, other) as sim:
+        chosen = sim.autotune(reps=1)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2
+    assert lines[1].split() == [arch, "2", "64", "1", "333", "333", "333", *map(str, chosen)]
