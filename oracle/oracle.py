@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("n_out", ctypes.POINTER(ctypes.c_uint64)),
         ("pair_out", ctypes.POINTER(ctypes.c_uint64)),
         ("connected", ctypes.c_int32),
+        ("mask_bits", ctypes.c_int32),
     ]
 
 
@@ -73,6 +74,10 @@ def lib():
         L.orc_threshold.restype = u64
         L.orc_decide.argtypes = [u64, u64, u32, u64, ctypes.c_int]
         L.orc_decide.restype = ctypes.c_int
+        L.orc_threshold_m.argtypes = [ctypes.c_double, ctypes.c_int]
+        L.orc_threshold_m.restype = u64
+        L.orc_decide_m.argtypes = [ctypes.POINTER(u64), ctypes.c_int, u32, u64, ctypes.c_int]
+        L.orc_decide_m.restype = ctypes.c_int
         L.orc_offset.argtypes = [u32, u32, u32, u64, u32]
         L.orc_offset.restype = u32
         L.orc_rule_window.argtypes = [ctypes.c_int, u32, ctypes.c_int, ctypes.c_int,
@@ -108,6 +113,17 @@ def decide(x1: int, x2: int, g: int, K: int, b: int) -> int:
     return int(lib().orc_decide(x1, x2, g, K, b))
 
 
+def threshold_m(q: float, m: int) -> int:
+    """K = rint(q * 2^(32+m)) for m decorrelation bits (2 or 4)."""
+    return int(lib().orc_threshold_m(float(q), int(m)))
+
+
+def decide_m(xs, g: int, K: int, b: int) -> int:
+    """U_b < K with U_b = (bits b of xs[0..m-1], most significant first) * 2^32 + g."""
+    arr = (ctypes.c_uint64 * len(xs))(*[int(x) for x in xs])
+    return int(lib().orc_decide_m(arr, len(xs), int(g), int(K), int(b)))
+
+
 def offset(seed: int, stream: int, plane: int, s: int, B: int) -> int:
     return int(lib().orc_offset(seed, stream, plane, s, B))
 
@@ -125,7 +141,7 @@ class Run:
 
     def __init__(self, *, model="pcpd", B=64, L, seed=1, stream=0, plane=0, p, d,
                  samples=(1 << 64) - 1, init="full", init_words=None, t0=0, times,
-                 connected=False):
+                 connected=False, mask_bits=2):
         self.times = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
         self.words = np.zeros(int(L), dtype=np.uint64)
         self.n = np.zeros((len(self.times), 64), dtype=np.uint64)
@@ -154,6 +170,7 @@ class Run:
         P.n_out = _ptr(self.n)
         P.pair_out = _ptr(self.pair)
         P.connected = 1 if connected else 0
+        P.mask_bits = int(mask_bits)
         self.params = P
 
     # aggregated observables over the simulated samples, per record

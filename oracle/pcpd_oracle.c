@@ -44,15 +44,20 @@
  *          window k, draw 0:  (k, 8q+0, lo32 s, hi32 s) -> X1_D, X2_D
  *          window k, draw 1:  (k, 8q+1, ...)            -> X1_A, X2_A
  *          window k, draw 2:  (k, 8q+2, ...)            -> R, gD, gA
- *        with X1 = x0 | x1<<32, X2 = x2 | x3<<32, R = x0 | x1<<32, gD = x2,
- *        gA = x3. Bit b of each 64-bit word belongs to sample b.
+ *          with m = 4 decorrelation bits also
+ *          window k, draw 3:  (k, 8q+3, ...)            -> X3_D, X4_D
+ *          window k, draw 4:  (k, 8q+4, ...)            -> X3_A, X4_A
+ *        with X1 = x0 | x1<<32, X2 = x2 | x3<<32 (X3, X4 likewise), R = x0 |
+ *        x1<<32, gD = x2, gA = x3. Bit b of each 64-bit word belongs to sample b.
  *   Probability-q decisions ......... the paper builds probability-d and
  *        probability-p bits from AND/OR of random words (Sec. 4.2) and from
  *        one word-wide comparison RNG() < 4p shared by all bits (Sec. 4.3).
- *        Generalised here to any q in [0,1]: sample b draws the 34-bit
- *        integer U_b = (2*bit_b(X1) + bit_b(X2)) * 2^32 + g, with g shared
- *        by the 64 samples of that word, and decides U_b < K with
- *        K = rint(q * 2^34). R_b = 1 means fission high.
+ *        Generalised here to any q in [0,1]: sample b draws the (32+m)-bit
+ *        integer U_b = u_b * 2^32 + g, where u_b is the m-bit number whose
+ *        bits, most significant first, are bit b of X1 .. Xm (m independent
+ *        bits per sample: the paper's decorrelation bits, m = 2 by default,
+ *        or 4) and g is shared by the 64 samples of that word, and decides
+ *        U_b < K with K = rint(q * 2^(32+m)). R_b = 1 means fission high.
  *   Observables ..................... paper Sec. 5.3: particle density and
  *        pair density. Per sample, N = number of occupied sites and
  *        N_pair = number of nearest-neighbour pairs (j, j+1 mod L) that are
@@ -124,6 +129,26 @@ int orc_decide(uint64_t x1, uint64_t x2, uint32_t g, uint64_t K, int b)
     return U < K ? 1 : 0;
 }
 
+/* K = rint(q * 2^(32+m)) for m decorrelation bits (2 or 4); UINT64_MAX for a
+ * bad q or m. */
+uint64_t orc_threshold_m(double q, int m)
+{
+    if (!(q >= 0.0 && q <= 1.0) || (m != 2 && m != 4))
+        return UINT64_MAX;
+    return (uint64_t)rint(ldexp(q, 32 + m));
+}
+
+/* Decision bit of sample b with m bits: U_b = u * 2^32 + g, u = bit b of
+ * x[0] .. x[m-1] read as an m-bit number, x[0] most significant. */
+int orc_decide_m(const uint64_t *x, int m, uint32_t g, uint64_t K, int b)
+{
+    uint64_t u = 0;
+    int i;
+    for (i = 0; i < m; i++)
+        u = 2u * u + ((x[i] >> b) & 1u);
+    return ((u << 32) + (uint64_t)g) < K ? 1 : 0;
+}
+
 /* Offset o of substep s of plane q: uniform in [0, B). */
 uint32_t orc_offset(uint32_t seed, uint32_t stream, uint32_t plane, uint64_t s, uint32_t B)
 {
@@ -136,12 +161,12 @@ uint32_t orc_offset(uint32_t seed, uint32_t stream, uint32_t plane, uint64_t s, 
 
 /* The three draws of window k of plane q in substep s. */
 typedef struct {
-    uint64_t x1d, x2d, x1a, x2a, r;
+    uint64_t xd[4], xa[4], r;  /* X1..Xm of the diffusion and annihilation decisions */
     uint32_t gd, ga;
 } orc_draws;
 
 static orc_draws window_draws(uint32_t seed, uint32_t stream, uint32_t plane, uint64_t s,
-                              uint32_t k)
+                              uint32_t k, int m)
 {
     orc_draws w;
     uint32_t key[2] = {seed, stream};
@@ -152,19 +177,31 @@ static orc_draws window_draws(uint32_t seed, uint32_t stream, uint32_t plane, ui
 
     ctr[1] = (plane << 3) | 0u;
     orc_philox4x32_10(ctr, key, x);
-    w.x1d = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
-    w.x2d = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+    w.xd[0] = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    w.xd[1] = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
 
     ctr[1] = (plane << 3) | 1u;
     orc_philox4x32_10(ctr, key, x);
-    w.x1a = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
-    w.x2a = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+    w.xa[0] = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    w.xa[1] = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
 
     ctr[1] = (plane << 3) | 2u;
     orc_philox4x32_10(ctr, key, x);
     w.r = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
     w.gd = x[2];
     w.ga = x[3];
+
+    w.xd[2] = w.xd[3] = w.xa[2] = w.xa[3] = 0;
+    if (m == 4) {
+        ctr[1] = (plane << 3) | 3u;
+        orc_philox4x32_10(ctr, key, x);
+        w.xd[2] = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+        w.xd[3] = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+        ctr[1] = (plane << 3) | 4u;
+        orc_philox4x32_10(ctr, key, x);
+        w.xa[2] = (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+        w.xa[3] = (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+    }
     return w;
 }
 
@@ -232,6 +269,7 @@ typedef struct {
     uint64_t *n_out;       /* [n_times][64] particles per sample */
     uint64_t *pair_out;    /* [n_times][64] pairs per sample */
     int32_t connected;     /* 1: the 64 bits form one joined lattice (orc_simulate_connected) */
+    int32_t mask_bits;     /* decorrelation bits m of every decision: 2 (also for 0) or 4 */
 } orc_params;
 
 static int orc_simulate_connected(const orc_params *P);
@@ -245,12 +283,14 @@ int orc_simulate(const orc_params *P)
     uint64_t Kd, Kp, t, j;
     uint32_t r, k;
     uint64_t nblocks;
+    int m;
 
     if (!P || P->n < 1 || P->n > 4 || P->B < (uint32_t)(P->n + 2) || P->L < P->B ||
         P->L % P->B != 0 || (P->L / P->B) > 0xffffffffull || P->plane >= (1u << 29))
         return -1;
-    Kd = orc_threshold(P->d);
-    Kp = orc_threshold(P->p);
+    m = P->mask_bits ? P->mask_bits : 2;
+    Kd = orc_threshold_m(P->d, m);
+    Kp = orc_threshold_m(P->p, m);
     if (Kd == UINT64_MAX || Kp == UINT64_MAX)
         return -1;
     if (P->init == 2 && !P->init_words)
@@ -292,12 +332,12 @@ int orc_simulate(const orc_params *P)
                 uint64_t s = t * (uint64_t)P->B + sub;
                 uint32_t o = orc_offset(P->seed, P->stream, P->plane, s, P->B);
                 for (k = 0; k < nblocks; k++) {
-                    orc_draws w = window_draws(P->seed, P->stream, P->plane, s, k);
+                    orc_draws w = window_draws(P->seed, P->stream, P->plane, s, k, m);
                     uint64_t site = (uint64_t)k * P->B + o;
                     for (b = 0; b < nsim; b++) {
                         int sb = idx[b];
-                        int D = orc_decide(w.x1d, w.x2d, w.gd, Kd, sb);
-                        int A = orc_decide(w.x1a, w.x2a, w.ga, Kp, sb);
+                        int D = orc_decide_m(w.xd, m, w.gd, Kd, sb);
+                        int A = orc_decide_m(w.xa, m, w.ga, Kp, sb);
                         int R = (int)((w.r >> sb) & 1u);
                         attempt(P->n, lat[sb], P->L, site, D, A, R);
                     }
@@ -363,23 +403,31 @@ done:
  * ------------------------------------------------------------------------- */
 
 /* One substep s of the Sec. 3 scheme on a joined ring of M = 64 L sites held
- * as bytes (q[g] for global site g). */
-void orc_connected_substep(int n, uint32_t B, uint64_t L, uint32_t seed, uint32_t stream,
-                           uint32_t plane, uint64_t Kd, uint64_t Kp, uint64_t s, uint8_t *q)
+ * as bytes (q[g] for global site g), with m decorrelation bits. */
+static void connected_substep_m(int n, uint32_t B, uint64_t L, uint32_t seed, uint32_t stream,
+                                uint32_t plane, uint64_t Kd, uint64_t Kp, uint64_t s, uint8_t *q,
+                                int m)
 {
     uint64_t nblocks = L / B, M = 64u * L, k;
     uint32_t o = orc_offset(seed, stream, plane, s, B);
     int b;
     for (k = 0; k < nblocks; k++) {
-        orc_draws w = window_draws(seed, stream, plane, s, (uint32_t)k);
+        orc_draws w = window_draws(seed, stream, plane, s, (uint32_t)k, m);
         for (b = 0; b < 64; b++) {
             uint64_t g = (uint64_t)b * L + k * B + o; /* global block b*nblocks + k */
-            int D = orc_decide(w.x1d, w.x2d, w.gd, Kd, b);
-            int A = orc_decide(w.x1a, w.x2a, w.ga, Kp, b);
+            int D = orc_decide_m(w.xd, m, w.gd, Kd, b);
+            int A = orc_decide_m(w.xa, m, w.ga, Kp, b);
             int R = (int)((w.r >> b) & 1u);
             attempt(n, q, M, g, D, A, R);
         }
     }
+}
+
+/* The same with m = 2 (exported for the tests of the layout). */
+void orc_connected_substep(int n, uint32_t B, uint64_t L, uint32_t seed, uint32_t stream,
+                           uint32_t plane, uint64_t Kd, uint64_t Kp, uint64_t s, uint8_t *q)
+{
+    connected_substep_m(n, B, L, seed, stream, plane, Kd, Kp, s, q, 2);
 }
 
 static int orc_simulate_connected(const orc_params *P)
@@ -387,9 +435,9 @@ static int orc_simulate_connected(const orc_params *P)
     uint64_t M = 64u * P->L, Kd, Kp, t, j, g;
     uint8_t *q;
     uint32_t r, sub;
-    int b;
-    Kd = orc_threshold(P->d);
-    Kp = orc_threshold(P->p);
+    int b, m = P->mask_bits ? P->mask_bits : 2;
+    Kd = orc_threshold_m(P->d, m);
+    Kp = orc_threshold_m(P->p, m);
     if (Kd == UINT64_MAX || Kp == UINT64_MAX)
         return -1;
     q = (uint8_t *)malloc(M);
@@ -409,8 +457,8 @@ static int orc_simulate_connected(const orc_params *P)
     for (r = 0; r < P->n_times; r++) {
         for (; t < P->times[r]; t++)
             for (sub = 0; sub < P->B; sub++)
-                orc_connected_substep(P->n, P->B, P->L, P->seed, P->stream, P->plane, Kd, Kp,
-                                      t * (uint64_t)P->B + sub, q);
+                connected_substep_m(P->n, P->B, P->L, P->seed, P->stream, P->plane, Kd, Kp,
+                                    t * (uint64_t)P->B + sub, q, m);
         for (b = 0; b < 64; b++) {
             uint64_t cnt = 0, pairs = 0;
             for (j = 0; j < P->L; j++) {
