@@ -93,6 +93,12 @@ typedef struct {
     uint32_t planes;  /* planes per instance, >= 1; 64 samples (or one joined ring) each */
     uint32_t seed;    /* Philox key word 0 */
     uint32_t layout;  /* pcpd_layout */
+    uint32_t mask_bits; /* decorrelation bits m of every decision (Sec. 4.3): 2 (also for 0)
+                           or 4. Sample b of a probability-q decision fires iff
+                           u_b * 2^32 + g < rint(q * 2^(32+m)), u_b the m-bit number of bit b
+                           of m independent random words and g a 32-bit part shared by the
+                           word's 64 samples; m = 4 takes two more Philox draws per window.
+                           Other values: PCPD_EINVAL. */
 } pcpd_config;
 
 /* One independent simulation (its own rates, ring length and Philox stream). */

@@ -97,37 +97,59 @@ def run_near_pc(p: float, d: float, L: int = 1 << 18, runs: int = 16, planes: in
     return curves_from_counts(times, counts, L, planes)
 
 
+def _deviations(per_run, ref, runs):
+    """Largest |mean difference| / its standard error over the records, per key."""
+    dev = {}
+    for k, r in per_run.items():
+        sigma = np.sqrt(r.var(axis=1, ddof=1) / runs + per_run[ref].var(axis=1, ddof=1) / runs)
+        diff = np.abs(r.mean(axis=1) - per_run[ref].mean(axis=1))
+        z = np.where(sigma > 0, diff / np.maximum(sigma, 1e-300), 0.0)
+        dev[k] = float(z.max())
+    return dev
+
+
+def _scheme_runs(p, d, L, runs, planes, steps, B, layout, mask_bits):
+    from . import pcpd
+
+    times = workloads.log_times(steps, 64)
+    insts = [workloads.Instance(float(p), float(d), int(L), k) for k in range(runs)]
+    with pcpd.Sim(workloads.PCPD, int(B), planes, 7, insts, layout=layout,
+                  mask_bits=mask_bits) as sim:
+        sim.set_options(graph=True)
+        c = sim.run(times)
+    return times, c
+
+
 def compare_block_widths(p: float, d: float, widths=(16, 64, 256), L: int = 1 << 18,
                          runs: int = 16, planes: int = 1, steps: int = 100_000, span: int = 4,
-                         layout: int = 0):
+                         layout: int = 0, mask_bits: int = 2):
     """The paper's numerical-accuracy check (Sec. 5.2): rho(t) near p_c for
     several block widths B (the number of sites that share one randomly chosen
     local site per substep; the paper's workgroup sizes 512 .. 32 at its
     L = 2^18 correspond to B = 16 .. 256). The same runs (Philox streams) at
-    every B; returns {B: Curves} and, per B, the largest relative deviation of
-    rho(t) from the curve at the largest B, in units of the statistical error
-    of the mean over runs at that record."""
-    from . import pcpd
-
-    times = workloads.log_times(steps, 64)
-    out, counts_by_B = {}, {}
+    every B; returns {B: Curves} and, per B, the largest deviation of rho(t)
+    from the curve at the largest B, in units of the statistical error of the
+    difference of the two means over runs at that record."""
+    out, per_run = {}, {}
     for B in widths:
-        insts = [workloads.Instance(float(p), float(d), int(L), k) for k in range(runs)]
-        with pcpd.Sim(workloads.PCPD, int(B), planes, 7, insts, layout=layout) as sim:
-            sim.set_options(graph=True)
-            c = sim.run(times)
-        counts_by_B[B] = c
+        times, c = _scheme_runs(p, d, L, runs, planes, steps, B, layout, mask_bits)
         out[B] = curves_from_counts(times, c, L, planes)
-    ref = max(widths)
-    per_run = {B: counts_by_B[B][:, :, :, 0].astype(np.float64).sum(axis=2) / (64.0 * planes * L)
-               for B in widths}
-    dev = {}
-    for B in widths:
-        sigma = np.sqrt(per_run[B].var(axis=1, ddof=1) / runs + per_run[ref].var(axis=1, ddof=1) / runs)
-        diff = np.abs(per_run[B].mean(axis=1) - per_run[ref].mean(axis=1))
-        z = np.where(sigma > 0, diff / np.maximum(sigma, 1e-300), 0.0)
-        dev[B] = float(z.max())
-    return out, dev
+        per_run[B] = c[:, :, :, 0].astype(np.float64).sum(axis=2) / (64.0 * planes * L)
+    return out, _deviations(per_run, max(widths), runs)
+
+
+def compare_mask_bits(p: float, d: float, bits=(2, 4), L: int = 1 << 18, runs: int = 16,
+                      planes: int = 1, steps: int = 100_000, B: int = 64, layout: int = 0):
+    """The other half of the Sec. 5.2 check: rho(t) near p_c with m = 2 and
+    m = 4 decorrelation bits per decision (independent random bits per sample
+    under the word-wide comparison), the same streams; deviations from the
+    largest m as in compare_block_widths."""
+    out, per_run = {}, {}
+    for m in bits:
+        times, c = _scheme_runs(p, d, L, runs, planes, steps, B, layout, m)
+        out[m] = curves_from_counts(times, c, L, planes)
+        per_run[m] = c[:, :, :, 0].astype(np.float64).sum(axis=2) / (64.0 * planes * L)
+    return out, _deviations(per_run, max(bits), runs)
 
 
 def main(argv: Optional[Sequence[str]] = None):
@@ -147,7 +169,22 @@ def main(argv: Optional[Sequence[str]] = None):
     ap.add_argument("--layout", type=int, default=0, help="0 classical, 1 connected (Sec. 4)")
     ap.add_argument("--compare-B", type=str, default=None,
                     help="comma-separated block widths: the Sec. 5.2 accuracy check instead")
+    ap.add_argument("--compare-m", type=str, default=None,
+                    help="comma-separated decorrelation bits (2,4): the same check over m")
     a = ap.parse_args(argv)
+    if a.compare_m:
+        bits = tuple(int(v) for v in a.compare_m.split(","))
+        curves, dev = compare_mask_bits(a.p, a.d, bits, a.L, a.runs, a.planes, a.steps,
+                                        layout=a.layout)
+        for m in bits:
+            t, r, de = curves[m].particle(a.span)
+            print(f"m={m}: rho(T)={curves[m].rho[-1]:.6g}, late delta_eff={de[-1]:.3f}, "
+                  f"largest |rho - rho(m={max(bits)})| / sigma = {dev[m]:.2f}", flush=True)
+        print(json.dumps({"p": a.p, "d": a.d, "L": a.L, "runs": a.runs, "steps": a.steps,
+                          "deviation_sigma": {str(k): v for k, v in dev.items()},
+                          "rho": {str(m): curves[m].rho.tolist() for m in bits},
+                          "times": curves[bits[0]].times.tolist()}), flush=True)
+        return
     if a.compare_B:
         widths = tuple(int(v) for v in a.compare_B.split(","))
         curves, dev = compare_block_widths(a.p, a.d, widths, a.L, a.runs, a.planes, a.steps,

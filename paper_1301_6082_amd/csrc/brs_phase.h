@@ -81,15 +81,17 @@ struct Masks {
     W2 D, Am, R;
 };
 
-// The ten rounds of the three draws of one window, advanced round by round
-// together: six independent 32x32->64 products per round. The first round's
-// products are identical for the three draws (they differ only in counter
-// word 1) and are computed once by the compiler.
-__device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb) {
+// The ten rounds of the draws of one window (three; five with four
+// decorrelation bits), advanced round by round together: two independent
+// 32x32->64 products per draw and round. The first round's products are
+// identical for all the draws (they differ only in counter word 1) and are
+// computed once by the compiler.
+template <int ND>
+__device__ __forceinline__ void philox10_xn(U4 (&c)[ND], uint32_t ka, uint32_t kb) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < ND; ++j) {
             const uint64_t pa = static_cast<uint64_t>(c[j].x) * kMulA;
             const uint64_t pb = static_cast<uint64_t>(c[j].z) * kMulB;
             U4 nx;
@@ -114,20 +116,20 @@ __device__ __forceinline__ void philox10_x3(U4 (&c)[3], uint32_t ka, uint32_t kb
 }
 
 // Draw identity of a lane's window: its block k. In the connected layout a
-// tile with columns past the ends of the word ring runs with LapWin, which
-// also carries the lap of the lane's column (a right rotation by rot = lap mod
-// 64; zero for columns inside the ring); every other tile runs with PlainWin,
-// whose code has no trace of the rotation.
-struct PlainWin {
-    static constexpr bool kLapped = false;
+// tile with columns past the ends of the word ring runs with a lapped window
+// type, which also carries the lap of the lane's column (a right rotation by
+// rot = lap mod 64; zero for columns inside the ring); every other tile runs
+// with PlainWin, whose code has no trace of the rotation. WIDE: decisions
+// with four decorrelation bits instead of two (two more draws per window).
+template <bool LAP, bool WIDE>
+struct WinT {
+    static constexpr bool kLapped = LAP;
+    static constexpr bool kWide = WIDE;
     uint32_t k;
-    uint32_t rot;  // unused
+    uint32_t rot;  // used when LAP
 };
-struct LapWin {
-    static constexpr bool kLapped = true;
-    uint32_t k;
-    uint32_t rot;
-};
+using PlainWin = WinT<false, false>;
+using LapWin = WinT<true, false>;
 
 // Right rotation of a 64-bit mask held as two halves, by r in 0..63.
 __device__ __forceinline__ W2 rotr_w2(W2 x, uint32_t r) {
@@ -136,13 +138,58 @@ __device__ __forceinline__ W2 rotr_w2(W2 x, uint32_t r) {
     return W2{__builtin_amdgcn_alignbit(hi, lo, r & 31u), __builtin_amdgcn_alignbit(lo, hi, r & 31u)};
 }
 
+// Probability decision with four decorrelation bits, one 32-bit half: bit i
+// fires iff u_i < kh or (u_i == kh and t_i), u_i the 4-bit number of bit i of
+// (a, b, c, d), a most significant; kh (0..16) is uniform across the wave.
+__device__ __forceinline__ uint32_t decide_wide(uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                                uint32_t t, uint32_t kh) {
+    if (kh >= 16u) return 0xFFFFFFFFu;
+    const uint32_t x[4] = {a, b, c, d};
+    uint32_t lt = 0u, eq = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if ((kh >> (3 - i)) & 1u) {
+            lt |= eq & ~x[i];
+            eq &= x[i];
+        } else {
+            eq &= ~x[i];
+        }
+    }
+    return lt | (eq & t);
+}
+
 template <int KDH, int KPH, typename Win>
 __device__ __forceinline__ Masks window_masks(const LatDesc &ld, Win w, uint64_t s) {
     const uint32_t slo = static_cast<uint32_t>(s), shi = static_cast<uint32_t>(s >> 32);
     const uint32_t q8 = ld.plane << 3;
     const uint32_t k = w.k;
+    if constexpr (Win::kWide) {
+        // m = 4: X1, X2 from draws 0 (D) and 1 (A), X3, X4 from draws 3 (D)
+        // and 4 (A); draw 2 as for m = 2. Sample b fires iff its four bits,
+        // X1 most significant, read below the threshold's integer part, or
+        // equal to it with the shared tail below its low word.
+        U4 x[5] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi},
+                   U4{k, q8 | 3u, slo, shi}, U4{k, q8 | 4u, slo, shi}};
+        philox10_xn<5>(x, ld.key0, ld.key1);
+        const U4 &d = x[0], &a = x[1], &r = x[2], &d2 = x[3], &a2 = x[4];
+        const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;
+        const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
+        Masks m;
+        m.D.lo = decide_wide(d.x, d.z, d2.x, d2.z, td, ld.kd_hi);
+        m.D.hi = decide_wide(d.y, d.w, d2.y, d2.w, td, ld.kd_hi);
+        m.Am.lo = decide_wide(a.x, a.z, a2.x, a2.z, ta, ld.kp_hi);
+        m.Am.hi = decide_wide(a.y, a.w, a2.y, a2.w, ta, ld.kp_hi);
+        m.R.lo = r.x;
+        m.R.hi = r.y;
+        if constexpr (Win::kLapped) {
+            m.D = rotr_w2(m.D, w.rot);
+            m.Am = rotr_w2(m.Am, w.rot);
+            m.R = rotr_w2(m.R, w.rot);
+        }
+        return m;
+    }
     U4 x[3] = {U4{k, q8 | 0u, slo, shi}, U4{k, q8 | 1u, slo, shi}, U4{k, q8 | 2u, slo, shi}};
-    philox10_x3(x, ld.key0, ld.key1);
+    philox10_xn<3>(x, ld.key0, ld.key1);
     const U4 &d = x[0], &a = x[1], &r = x[2];
     const uint32_t td = (r.z < ld.kd_lo) ? 0xFFFFFFFFu : 0u;  // shared tails gD, gA
     const uint32_t ta = (r.w < ld.kp_lo) ? 0xFFFFFFFFu : 0u;
@@ -761,10 +808,19 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
         if (kb >= nb) kb %= nb;
         if constexpr (GENERAL) {
             const int64_t v0 = static_cast<int64_t>(td.k0) - hb;
-            if (ld.connected &&
-                (v0 < 0 || v0 + static_cast<int64_t>(ncols) > static_cast<int64_t>(nb))) {
-                const uint32_t rot =
-                    c < ncols ? static_cast<uint32_t>(ring_lap(v0 + c, nb)) & 63u : 0u;
+            const bool lapped =
+                ld.connected && (v0 < 0 || v0 + static_cast<int64_t>(ncols) > static_cast<int64_t>(nb));
+            const uint32_t rot =
+                lapped && c < ncols ? static_cast<uint32_t>(ring_lap(v0 + c, nb)) & 63u : 0u;
+            if (ld.mbits == 4u) {
+                // the decision reads the thresholds at run time: one loop copy
+                if (lapped)
+                    run_team_loop<N, 0, 0, T>(lds, ld, WinT<true, true>{kb, rot}, c, team, ncols,
+                                              trash, s0, S, B, ldw);
+                else
+                    run_team_loop<N, 0, 0, T>(lds, ld, WinT<false, true>{kb, 0u}, c, team, ncols,
+                                              trash, s0, S, B, ldw);
+            } else if (lapped) {
                 dispatch_kd<N, T>(lds, ld, LapWin{kb, rot}, c, team, ncols, trash, s0, S, B, ldw);
             } else {
                 dispatch_kd<N, T>(lds, ld, PlainWin{kb, 0u}, c, team, ncols, trash, s0, S, B, ldw);

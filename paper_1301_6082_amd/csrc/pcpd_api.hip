@@ -42,6 +42,7 @@ struct pcpd_ctx {
     uint64_t total_words = 0;        // planes * sum L
     uint32_t nlat = 0;               // n_inst * planes
     bool connected = false;          // connected multispin layout (pcpd_config.layout)
+    bool wide = false;               // four decorrelation bits (pcpd_config.mask_bits)
 
     hipStream_t stream = nullptr;
     uint64_t *buf[2] = {nullptr, nullptr};
@@ -104,9 +105,14 @@ constexpr uint32_t kDenChunkWords = 8192;
 constexpr uint32_t kPersistSpinLimit = 1u << 20;
 constexpr size_t kMaxGraphs = 16;
 
-// K = rint(q * 2^34): the integer threshold of a probability-q decision.
-// ldexp is exact and rint rounds half to even.
-uint64_t rate_threshold(double q) { return static_cast<uint64_t>(std::rint(std::ldexp(q, 34))); }
+// K = rint(q * 2^(32+m)): the integer threshold of a probability-q decision
+// with m decorrelation bits. ldexp is exact and rint rounds half to even.
+uint64_t rate_threshold(double q, uint32_t m) {
+    return static_cast<uint64_t>(std::rint(std::ldexp(q, 32 + static_cast<int>(m))));
+}
+
+// m of a configuration (0 means the default, 2).
+uint32_t mask_bits_of(const pcpd_config *cfg) { return cfg->mask_bits ? cfg->mask_bits : 2u; }
 
 bool rate_ok(double q) { return std::isfinite(q) && q >= 0.0 && q <= 1.0; }
 
@@ -118,6 +124,7 @@ int validate(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t n_inst,
     if (cfg->model < 1 || cfg->model > 4) return PCPD_EINVAL;
     if (cfg->layout != PCPD_LAYOUT_CLASSICAL && cfg->layout != PCPD_LAYOUT_CONNECTED)
         return PCPD_EINVAL;
+    if (mask_bits_of(cfg) != 2u && mask_bits_of(cfg) != 4u) return PCPD_EINVAL;
     const uint32_t n = static_cast<uint32_t>(cfg->model);
     if (cfg->B < n + 2 || cfg->planes == 0 || cfg->planes >= (1u << 29)) return PCPD_EINVAL;
     uint64_t total = 0;
@@ -272,7 +279,8 @@ std::vector<LatDesc> plan_lats(const pcpd_config *cfg, const pcpd_instance *inst
     std::vector<LatDesc> lats;
     uint64_t base = 0;
     for (uint32_t i = 0; i < n_inst; ++i) {
-        const uint64_t kd = rate_threshold(inst[i].d), kp = rate_threshold(inst[i].p);
+        const uint32_t m = mask_bits_of(cfg);
+        const uint64_t kd = rate_threshold(inst[i].d, m), kp = rate_threshold(inst[i].p, m);
         for (uint32_t q = 0; q < cfg->planes; ++q) {
             LatDesc ld{};
             ld.base = base + q * inst[i].L;
@@ -286,6 +294,7 @@ std::vector<LatDesc> plan_lats(const pcpd_config *cfg, const pcpd_instance *inst
             ld.kp_hi = static_cast<uint32_t>(kp >> 32);
             ld.kp_lo = static_cast<uint32_t>(kp);
             ld.connected = cfg->layout == PCPD_LAYOUT_CONNECTED ? 1u : 0u;
+            ld.mbits = m;
             lats.push_back(ld);
         }
         base += inst[i].L * cfg->planes;
@@ -378,7 +387,7 @@ hipError_t enqueue_ops(pcpd_ctx *ctx, const std::vector<BatchOp> &ops, hipStream
             pcpd::kMaxLdsBytes;
     PhaseShape shape = ctx->shape;
     shape.skip_empty = (ctx->options & PCPD_OPT_SKIP_EMPTY) ? 1u : 0u;
-    shape.general = (shape.skip_empty || ctx->connected) ? 1u : 0u;
+    shape.general = (shape.skip_empty || ctx->connected || ctx->wide) ? 1u : 0u;
     for (const BatchOp &op : ops) {
         const uint64_t end = rel + op.steps * ctx->B;
         if (persistent && end > rel) {
@@ -676,7 +685,7 @@ hipError_t search_shape(pcpd_ctx *ctx, uint32_t reps, PhaseShape *best, uint32_t
             ctx->shape = sh;
             // time the kernel copy the context's runs will use
             sh.skip_empty = (ctx->options & PCPD_OPT_SKIP_EMPTY) ? 1u : 0u;
-            sh.general = (sh.skip_empty || ctx->connected) ? 1u : 0u;
+            sh.general = (sh.skip_empty || ctx->connected || ctx->wide) ? 1u : 0u;
             ctx->phase_max = pm;
             if ((e = build_tiles(ctx)) != hipSuccess) break;
             float ms = 0.0f;
@@ -798,6 +807,7 @@ int pcpd_init(pcpd_ctx **out, const pcpd_config *cfg, const pcpd_instance *inst,
     if (!ctx) return PCPD_ENOMEM;
     ctx->n = cfg->model;
     ctx->connected = cfg->layout == PCPD_LAYOUT_CONNECTED;
+    ctx->wide = mask_bits_of(cfg) == 4u;
     ctx->B = cfg->B;
     ctx->planes = cfg->planes;
     ctx->seed = cfg->seed;
@@ -1120,6 +1130,7 @@ int pcpd_run_noalloc(const pcpd_config *cfg, const pcpd_instance *inst, uint32_t
     c.shape = shape;
     c.phase_max = pmax;
     c.connected = cfg->layout == PCPD_LAYOUT_CONNECTED;
+    c.wide = mask_bits_of(cfg) == 4u;
 
     // The host tables are read by the copies before this call returns (it
     // synchronises below). Every count record is cleared by a kernel before

@@ -23,7 +23,7 @@ struct LatDesc {
     uint32_t kp_hi;    // annihilation threshold K_p
     uint32_t kp_lo;
     uint32_t connected;  // 1: the 64 bits form one joined ring of 64 L sites
-    uint32_t pad;
+    uint32_t mbits;      // decorrelation bits m of every decision: 2 or 4
 };
 
 // One workgroup's tile: interior blocks [k0, k0 + kint) of lattice `lat`.

@@ -32,7 +32,8 @@ LAYOUT_CLASSICAL, LAYOUT_CONNECTED = 0, 1
 
 
 class Config(ctypes.Structure):
-    _fields_ = [("model", i32), ("B", u32), ("planes", u32), ("seed", u32), ("layout", u32)]
+    _fields_ = [("model", i32), ("B", u32), ("planes", u32), ("seed", u32), ("layout", u32),
+                ("mask_bits", u32)]
 
 
 class InstanceC(ctypes.Structure):
@@ -150,8 +151,9 @@ def _instances(insts, planes):
     return arr, keep
 
 
-def lattice_bytes(model: int, B: int, planes: int, seed: int, instances, layout: int = 0) -> int:
-    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout))
+def lattice_bytes(model: int, B: int, planes: int, seed: int, instances, layout: int = 0,
+                  mask_bits: int = 2) -> int:
+    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout), int(mask_bits))
     arr, _ = _instances(instances, planes)
     out = ctypes.c_size_t()
     _check(_lib.pcpd_lattice_bytes(ctypes.byref(cfg), arr, len(instances), ctypes.byref(out)),
@@ -164,16 +166,18 @@ class Sim:
     p, d, L, stream_id, init, host_words) sharing model, B, planes and seed."""
 
     def __init__(self, model: int, B: int, planes: int, seed: int, instances, t0: int = 0,
-                 device: int | None = None, torch_buffer: bool = True, layout: int = 0):
+                 device: int | None = None, torch_buffer: bool = True, layout: int = 0,
+                 mask_bits: int = 2):
         if not torch.cuda.is_available():
             raise RuntimeError("libpcpd needs a ROCm GPU; none is visible")
         self.model, self.B, self.planes, self.seed = int(model), int(B), int(planes), int(seed)
         self.layout = int(layout)
+        self.mask_bits = int(mask_bits)
         self.instances = list(instances)
         self.n_inst = len(self.instances)
         self.Ls = [int(i.L) for i in self.instances]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-        cfg = Config(self.model, self.B, self.planes, self.seed, self.layout)
+        cfg = Config(self.model, self.B, self.planes, self.seed, self.layout, self.mask_bits)
         arr, keep = _instances(self.instances, self.planes)
         dev = Device()
         with torch.cuda.device(self.device):
@@ -182,7 +186,7 @@ class Sim:
             self._buf = None
             if torch_buffer:
                 nbytes = lattice_bytes(self.model, self.B, self.planes, self.seed, self.instances,
-                                       self.layout)
+                                       self.layout, self.mask_bits)
                 self._buf = torch.empty(nbytes // 8, dtype=torch.int64, device=self.device)
                 dev.dev_buf = ctypes.c_void_p(self._buf.data_ptr())
                 dev.dev_buf_bytes = nbytes
@@ -284,7 +288,8 @@ class Sim:
 
 
 def run_noalloc(model: int, B: int, planes: int, seed: int, instances, t0: int,
-                lattice: torch.Tensor, times: Sequence[int], layout: int = 0) -> np.ndarray:
+                lattice: torch.Tensor, times: Sequence[int], layout: int = 0,
+                mask_bits: int = 2) -> np.ndarray:
     """pcpd_run_noalloc: advance the lattice held in `lattice` (a contiguous
     int64 CUDA tensor of planes * sum L words, instance-major then
     plane-major) from step t0 through `times`, in place, without any device
@@ -294,7 +299,7 @@ def run_noalloc(model: int, B: int, planes: int, seed: int, instances, t0: int,
     if not (isinstance(lattice, torch.Tensor) and lattice.is_cuda and lattice.dtype == torch.int64
             and lattice.is_contiguous() and lattice.numel() == words):
         raise ValueError(f"lattice must be a contiguous int64 CUDA tensor of {words} words")
-    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout))
+    cfg = Config(int(model), int(B), int(planes), int(seed), int(layout), int(mask_bits))
     arr, keep = _instances(instances, planes)
     t = np.ascontiguousarray(np.asarray(times, dtype=np.uint64))
     out = (CountsC * (len(t) * len(instances) * planes))()

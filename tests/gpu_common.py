@@ -34,7 +34,7 @@ def aggregate_counts(words: np.ndarray):
 
 
 def oracle_runs(model, B, planes, seed, instances, times, t0=0, samples=(1 << 64) - 1,
-                which=None, init_words=None, connected=False):
+                which=None, init_words=None, connected=False, mask_bits=2):
     """One oracle.Run per (instance, plane) in `which` (default: all)."""
     runs = []
     keys = which if which is not None else [(i, q) for i in range(len(instances))
@@ -50,6 +50,6 @@ def oracle_runs(model, B, planes, seed, instances, times, t0=0, samples=(1 << 64
         runs.append(oracle.Run(model=MODEL_NAME[model], B=B, L=int(inst.L), seed=seed,
                                stream=int(inst.stream_id), plane=q, p=inst.p, d=inst.d,
                                samples=samples, init=init, init_words=iw, t0=t0, times=times,
-                               connected=connected))
+                               connected=connected, mask_bits=mask_bits))
     oracle.simulate_many(runs)
     return keys, runs

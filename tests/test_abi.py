@@ -149,3 +149,11 @@ def test_mlp_calls_refuse_bad_arguments_without_a_device(mod):
     lib = mod._lib
     f = ctypes.c_float()
     assert lib.pcpd_mlp_loss(None, None, None, None, 1, None, ctypes.byref(f)) == mod.PCPD_EINVAL
+
+
+def test_mask_bits_other_than_2_or_4_are_refused(mod):
+    out = ctypes.c_size_t()
+    for m, ok in ((0, True), (2, True), (4, True), (3, False), (1, False), (8, False)):
+        cfg = mod.Config(2, 64, 1, 1, 0, m)
+        st = mod._lib.pcpd_lattice_bytes(ctypes.byref(cfg), _inst(mod), 1, ctypes.byref(out))
+        assert (st == mod.PCPD_OK) == ok, m

@@ -31,3 +31,17 @@ def test_particle_and_pair_exponents_near_pc(curves):
         assert 0.05 < np.median(d[late]) < 0.45, name
     delta, _ = an.extrapolate(*curves.particle(4)[1:], rho_max=0.2)
     assert np.isfinite(delta)
+
+
+def test_mask_bit_comparison_runs_and_is_exact_at_quarter_rates():
+    """At rates in quarters m = 2 and m = 4 fire on the same bits (pinned in
+    the oracle), so the two curves coincide; elsewhere they are two valid
+    realizations with finite deviations."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    curves, dev = an.compare_mask_bits(0.25, 0.5, (2, 4), L=1 << 12, runs=4, steps=500)
+    np.testing.assert_array_equal(curves[2].rho, curves[4].rho)
+    assert dev[2] == 0.0
+    curves, dev = an.compare_mask_bits(0.13, 0.3, (2, 4), L=1 << 12, runs=4, steps=500)
+    assert not np.array_equal(curves[2].rho, curves[4].rho)
+    assert np.isfinite(dev[2]) and dev[4] == 0.0

@@ -23,12 +23,13 @@ def pcpd():
 
 
 def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t0=0,
-                  options=None, layout=0):
+                  options=None, layout=0, mask_bits=2):
     """GPU run with records at `times` vs the oracle on every plane, all samples."""
     print(f"[parity] model={model} B={B} planes={planes} n_inst={len(instances)} "
           f"L={[i.L for i in instances]} times={times[:4]}..{times[-1]} tuning={tuning} "
-          f"options={options} layout={layout}", flush=True)
-    with pcpd.Sim(model, B, planes, seed, instances, t0=t0, layout=layout) as sim:
+          f"options={options} layout={layout} mask_bits={mask_bits}", flush=True)
+    with pcpd.Sim(model, B, planes, seed, instances, t0=t0, layout=layout,
+                  mask_bits=mask_bits) as sim:
         if tuning:
             sim.set_tuning(*tuning)
         if options:
@@ -36,7 +37,7 @@ def _compare_full(pcpd, model, B, planes, seed, instances, times, tuning=None, t
         counts = sim.run(times)
         lat = [sim.get_lattice(i) for i in range(len(instances))]
     keys, runs = oracle_runs(model, B, planes, seed, instances, times, t0=t0,
-                             connected=layout == 1)
+                             connected=layout == 1, mask_bits=mask_bits)
     for (i, q), r in zip(keys, runs):
         L = instances[i].L
         np.testing.assert_array_equal(lat[i][q * L:(q + 1) * L], r.words,
@@ -482,3 +483,25 @@ def test_autotune_disk_cache_and_forced_shape(pcpd, tmp_path, monkeypatch):
     lines = cache.read_text().splitlines()
     assert len(lines) == 2
     assert lines[1].split() == [arch, "2", "64", "1", "333", "333", "333", *map(str, chosen)]
+
+
+# ---- four decorrelation bits ------------------------------------------------------
+
+@pytest.mark.parametrize("teams", [2, 4])
+@pytest.mark.parametrize("model", [1, 2, 3, 4])
+def test_four_decorrelation_bits_match_oracle(pcpd, model, teams):
+    """mask_bits = 4 (two more Philox draws per window, thresholds rint(q 2^36)):
+    rates in sixteenths and off them, the edges q = 0 and 1, many tiles and a
+    ragged tail."""
+    insts = [Instance(0.13, 0.37, 64 * 260, 1), Instance(0.0, 1.0, 64 * 40, 2),
+             Instance(1.0, 0.0, 64 * 30, 3), Instance(0.5625, 0.0625, 64 * 77, 4),
+             Instance(0.9, 0.6, 64 * 50, 5)]
+    _compare_full(pcpd, model, 64, 2, 8, insts, [1, 3, 7], tuning=(128, 64, teams), mask_bits=4)
+
+
+def test_four_decorrelation_bits_other_layouts_and_launches(pcpd):
+    insts = [Instance(0.2, 0.3, 64 * 150, 0), Instance(0.11, 0.5, 64 * 9, 1)]
+    _compare_full(pcpd, 2, 64, 1, 5, insts, [2, 6], mask_bits=4, layout=1)
+    _compare_full(pcpd, 2, 64, 1, 5, insts, [2, 6], tuning=(64, 16, 2), mask_bits=4,
+                  options={"persistent": True, "skip_empty": True})
+    _compare_full(pcpd, 3, 15, 2, 5, [Instance(0.17, 0.45, 15 * 333, 3)], [4], mask_bits=4)
