@@ -129,7 +129,9 @@ typedef struct {
 } pcpd_counts;
 
 /* Kernel shape of the sweep. Results never depend on it. All three 0 = the
- * default shape; otherwise a 0 field keeps the context's current value. */
+ * default shape (phases of at most 128 substeps, the widest tile of at most 128
+ * blocks that lets two workgroups share a CU, four teams); otherwise a 0 field
+ * keeps the context's current value. */
 typedef struct {
     uint32_t tile_cols;  /* blocks per workgroup tile including the halo */
     uint32_t phase_max;  /* substeps run while a tile stays in LDS */
