@@ -448,6 +448,26 @@ __device__ __forceinline__ uint32_t group_run_index(uint32_t sites, uint32_t B) 
 // of the run at once. A team draws the masks of its next substep (T later)
 // between the loads and the arithmetic of its update. Every wavefront passes
 // the same barriers: each computes the same cut from the same local sites.
+// Local sites and run indices of the batches of 64 substeps, shared by the
+// wavefronts of a four-team workgroup: two slots of (sites, runs) x 64 words
+// in LDS after the tile and its flag word. Batch 0 is written by wavefront 0
+// before the barrier that ends the tile load; batch b+1 by wavefront
+// (b+1) mod (wavefronts) at the start of batch b, and read at the start of
+// batch b+1, after the barriers of batch b. The slot it overwrites was last
+// read at the start of batch b-1, before those barriers.
+__device__ __forceinline__ uint32_t *batch_share(uint64_t *lds, uint32_t B, uint32_t ldw) {
+    return reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw + 1u);
+}
+
+template <int N, int T>
+__device__ __forceinline__ void write_batch(uint32_t *slot, const LatDesc &ld, uint64_t s,
+                                            uint32_t B) {
+    const uint32_t lane = __lane_id();
+    const uint32_t sites = substep_site(ld, s + lane, B);  // lane i: substep s + i
+    slot[lane] = sites;
+    slot[64u + lane] = group_run_index<N, T>(sites, B);
+}
+
 template <int N, int KDH, int KPH, int T, typename Win>
 __device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc &ld, Win kg,
                                                    uint32_t c, uint32_t team, uint32_t ncols,
@@ -481,9 +501,16 @@ __device__ __forceinline__ void run_substeps_teams(uint64_t *lds, const LatDesc 
             for (uint32_t e = 0; e < nseg; ++e) __syncthreads();
         }
     };
-    for (uint32_t it0 = 0; it0 < S; it0 += 64u) {
-        const uint32_t sites = substep_site(ld, s0 + it0 + lane, B);  // lane i: substep it0 + i
-        const uint32_t runs = group_run_index<N, T>(sites, B);
+    uint32_t *share = batch_share(lds, B, ldw);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nwaves = blockDim.x >> 6;
+    uint32_t b = 0;
+    for (uint32_t it0 = 0; it0 < S; it0 += 64u, ++b) {
+        const uint32_t *slot = share + (b & 1u) * 128u;
+        const uint32_t sites = slot[lane];        // lane i: local site of substep it0 + i
+        const uint32_t runs = slot[64u + lane];   // its run index within its group
+        if (it0 + 64u < S && wave == (b + 1u) % nwaves)
+            write_batch<N, T>(share + ((b + 1u) & 1u) * 128u, ld, s0 + it0 + 64u, B);
         const uint32_t n = (S - it0 < 64u) ? S - it0 : 64u;
         uint32_t g = 0;
         for (; g + T < n; g += 2u * T) {
@@ -757,11 +784,16 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
     // particle: cleared before the loads, set after the first barrier, read
     // after the second (no substep writes it).
     bool empty = false;
+    // four teams: wavefront 0 writes the shared sites of the first batch
+    // while the tile's loads are in flight (read after the barrier below)
     if (GENERAL && skip_empty) {
         uint32_t *flag = reinterpret_cast<uint32_t *>(lds + static_cast<size_t>(B) * ldw);
         if (tid == 0) *flag = 0u;
         load_tile_any<true>(lds, src + ld.base, pairs, fixed_row, kfirst, nb, ncols * B, B, ldw,
                             tid, nthr, any);
+        if constexpr (T != 2) {
+            if (tid < 64u) write_batch<N, T>(batch_share(lds, B, ldw), ld, s0, B);
+        }
         __syncthreads();
         if (__ballot(any != 0ull) != 0ull && (tid & 63u) == 0u) *flag = 1u;
         __syncthreads();
@@ -769,6 +801,9 @@ __device__ __forceinline__ void tile_phase(uint64_t *lds, const uint64_t *__rest
     } else {
         load_tile_any<false>(lds, src + ld.base, pairs, fixed_row, kfirst, nb, ncols * B, B, ldw,
                              tid, nthr, any);
+        if constexpr (T != 2) {
+            if (tid < 64u) write_batch<N, T>(batch_share(lds, B, ldw), ld, s0, B);
+        }
         __syncthreads();
     }
 

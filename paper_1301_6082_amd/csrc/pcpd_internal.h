@@ -131,7 +131,8 @@ hipError_t launch_fill(uint64_t *dst, uint64_t nwords, uint64_t value, hipStream
 hipError_t launch_density(const uint64_t *buf, const LatDesc *lats, const DenChunk *chunks,
                           uint32_t nchunks, Counts *out, uint32_t nlat, hipStream_t stream);
 
-// LDS of one phase workgroup: B x ldw lattice words and the empty-tile flag word.
+// LDS of one phase workgroup: B x ldw lattice words, the empty-tile flag word
+// and the shared substep sites of the four-team loop (1 KB).
 size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S);
 
 }  // namespace pcpd

@@ -69,8 +69,9 @@ __global__ void zero_counts(Counts *__restrict__ out, uint32_t nlat) {
 
 size_t phase_lds_bytes(uint32_t B, uint32_t ldw, uint32_t S) {
     (void)S;
-    // the tile, plus one word for the empty-tile flag
-    return (static_cast<size_t>(B) * ldw + 1) * sizeof(uint64_t);
+    // the tile, one word for the empty-tile flag, and the shared local sites
+    // and run indices of two batches of 64 substeps (four teams)
+    return (static_cast<size_t>(B) * ldw + 1) * sizeof(uint64_t) + 2u * 2u * 64u * sizeof(uint32_t);
 }
 
 hipError_t launch_phase(int n, const uint64_t *src, uint64_t *dst, const LatDesc *lats,
