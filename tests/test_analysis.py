@@ -59,3 +59,18 @@ def test_curves_from_counts():
     assert cv.runs == runs
     t, r, d = cv.particle()
     np.testing.assert_allclose(d, [np.log(2) / np.log(10), np.log(4) / np.log(10)])
+
+
+def test_deviation_statistic_is_the_largest_standardized_mean_difference():
+    """_deviations: per key, the largest over records of |mean_k - mean_ref| /
+    sqrt(var_k / R + var_ref / R) with sample variances over the R runs; the
+    reference itself deviates by 0."""
+    rng = np.random.default_rng(5)
+    R = 8
+    ref = rng.normal(1.0, 0.1, size=(3, R))
+    other = ref + np.array([[0.0], [0.05], [0.02]])     # shift records 1 and 2 only
+    dev = an._deviations({"a": other, "b": ref}, "b", R)
+    assert dev["b"] == 0.0
+    sd = np.sqrt(ref.var(axis=1, ddof=1) / R * 2)        # same spread in both (a shifted copy)
+    want = max(0.05 / sd[1], 0.02 / sd[2])
+    assert dev["a"] == pytest.approx(want, rel=1e-12)
